@@ -1,0 +1,85 @@
+"""The O3 structural checker accepts a hand-built EHYB encoding and rejects
+encodings with planted mistakes (mistakes planted in checker inputs, CPU only).
+
+Hand-built example (4x4, two partitions {0,1} and {2,3}, one lane per row,
+two entries per lane per step):
+
+    A = [[1 2 . 3]     row 0: ELL (0,0)=1 (0,1)=2, residual (0,3)=3
+         [4 5 . .]     row 1: ELL (1,0)=4 (1,1)=5
+         [. . 6 7]     row 2: ELL (2,2)=6 (2,3)=7
+         [8 . 9 10]]   row 3: ELL (3,2)=9 (3,3)=10, residual (3,0)=8
+"""
+import numpy as np
+import pytest
+
+import matgen
+from oracle.structure import PlanError, check_plan, layout_spmv
+
+
+def _tiny():
+    d = np.array([[1, 2, 0, 3], [4, 5, 0, 0], [0, 0, 6, 7], [8, 0, 9, 10]], dtype=np.float64)
+    A = matgen.from_dense(d)
+    ell_val = np.zeros(256)
+    ell_col = np.zeros(256, dtype=np.uint16)
+    for slot, v, c in [(0, 1, 0), (1, 2, 1), (2, 4, 0), (3, 5, 1),
+                       (128, 6, 0), (129, 7, 1), (130, 9, 0), (131, 10, 1)]:
+        ell_val[slot], ell_col[slot] = v, c
+    er_val = np.zeros(128)
+    er_col = np.zeros(128, dtype=np.int32)
+    er_val[0], er_col[0] = 3, 3
+    er_val[65], er_col[65] = 8, 0
+    view = dict(n=4, nparts=2, L=1, kc=2, perm=np.arange(4), part_start=np.array([0, 2, 4]),
+                slice_start=np.array([0, 1, 2]),
+                slice_meta=np.array([[0, 1, 0, 1], [128, 1, 64, 1]], dtype=np.uint32),
+                ell_val=ell_val, ell_col=ell_col, er_val=er_val, er_col=er_col,
+                row_ell_len=np.array([2, 2, 2, 2]), row_er_len=np.array([1, 0, 0, 1]))
+    return A, d, view
+
+
+def test_hand_built_plan_passes():
+    A, d, view = _tiny()
+    st = check_plan(A, view)
+    assert st["nnz_ell"] == 8 and st["nnz_er"] == 2 and st["nparts"] == 2
+    x = np.array([1.0, -2.0, 0.5, 3.0])
+    assert np.array_equal(layout_spmv(view, x), d @ x)
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda v: v["ell_val"].__setitem__(1, 2.5), "values differ"),
+    (lambda v: v["ell_val"].__setitem__(7, 1.0), "padding"),
+    (lambda v: v["ell_val"].__setitem__(7, -0.0), "padding"),
+    (lambda v: v["ell_col"].__setitem__(1, 3), "outside"),
+    (lambda v: v["er_col"].__setitem__(65, 1), "pattern differs"),
+    (lambda v: v["perm"].__setitem__(slice(0, 2), [1, 0]), ""),
+    (lambda v: v["row_er_len"].__setitem__(0, 0), ""),
+    (lambda v: v["slice_meta"].__setitem__((1, 0), 0), "overlapping"),
+    (lambda v: v["part_start"].__setitem__(1, 3), ""),
+])
+def test_planted_mistakes_are_caught(mutate, msg):
+    A, _, view = _tiny()
+    mutate(view)
+    with pytest.raises((PlanError, IndexError, ValueError)) as e:
+        check_plan(A, view)
+    assert msg in str(e.value)
+
+
+def test_intra_partition_entry_in_residual_is_caught():
+    """Move ELL entry (1,0) into the residual part: same content, wrong class."""
+    A, _, view = _tiny()
+    view["ell_val"][2], view["ell_val"][3] = 5, 0      # row 1 keeps only (1,1) ... shifted
+    view["ell_col"][2], view["ell_col"][3] = 1, 0
+    view["row_ell_len"][1] = 1
+    view["row_er_len"][1] = 1
+    view["er_val"][1], view["er_col"][1] = 4, 0
+    with pytest.raises(PlanError, match="intra-partition"):
+        check_plan(A, view)
+    # the same encoding is valid under a width cap of 1 for row 1 only if every
+    # row respects the cap, which rows 0, 2, 3 do not
+    with pytest.raises(PlanError):
+        check_plan(A, view, width_cap=1)
+
+
+def test_lds_budget_and_16bit_limit():
+    A, _, view = _tiny()
+    with pytest.raises(PlanError, match="on-chip"):
+        check_plan(A, view, tau_x=8, lds_budget=8)
