@@ -1,0 +1,246 @@
+/*
+ * ehyb.h - C ABI of the EHYB (explicit-caching hybrid) sparse matrix-vector
+ * product for AMD Instinct MI355X (gfx950).
+ *
+ * Operation (Introduction): y = A x, A a square sparse matrix, x and y dense
+ * vectors.  The method (Section 3) prepares A once on the host:
+ *   - A is read as an undirected graph whose vertices are the row/column
+ *     indices and whose edges are the stored entries (Section 3.1);
+ *   - the graph is cut into partitions small enough that each partition's
+ *     slice of x fits the on-chip cache of one workgroup (Section 3.3, Eq. 1-2);
+ *   - rows are renumbered partition by partition, and inside a partition by
+ *     non-increasing count of in-partition entries (Section 3.2, Alg. 1);
+ *   - in-partition entries are stored in a sliced-ELL part whose column
+ *     indices are 16-bit offsets into the partition's x-slice (Section 3.4);
+ *     all other entries go to the residual "extra rows" part with 32-bit
+ *     columns (Section 3.2, Alg. 2);
+ * and the device kernel (Section 4.2, Alg. 3) stages each x-slice in LDS,
+ * sweeps the ELL part against it and adds the residual part read against x
+ * in device memory.
+ *
+ * Conventions for every function below:
+ *   - Returns EHYB_OK or a negative ehyb_status; never aborts, never lets a
+ *     C++ exception escape.  On failure a message is available from
+ *     ehyb_last_error() (thread-local, valid until the next call on the same
+ *     thread) and outputs are left unspecified.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device allocations on the current device.  The library never allocates
+ *     device memory: the caller provides every device buffer.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Device work is enqueued on it and the call returns without waiting,
+ *     except where stated.
+ *   - Vectors are contiguous, dtype as stated (x, y FP64 for FP64 plans).
+ *     x and y must not overlap.  x is assumed finite: padding slots multiply
+ *     +0.0 by an x element, so an Inf or NaN in x may leak into rows that do
+ *     not reference it.
+ */
+#ifndef EHYB_H
+#define EHYB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define EHYB_API __attribute__((visibility("default")))
+
+typedef enum {
+    EHYB_OK = 0,
+    EHYB_EINVAL = -1,        /* malformed argument or input matrix */
+    EHYB_ENOMEM = -2,        /* host allocation failed */
+    EHYB_EUNSUPPORTED = -3,  /* valid but outside what the format supports */
+    EHYB_EDEVICE = -4,       /* a HIP call or kernel launch failed */
+    EHYB_ESTATE = -5         /* call out of order (e.g. spmv before upload) */
+} ehyb_status;
+
+/* Storage type of matrix values.  EHYB_F64: FP64 values, FP64 x/y/accumulate. */
+typedef enum { EHYB_F64 = 0, EHYB_F32 = 1, EHYB_BF16 = 2 } ehyb_dtype;
+
+/* Which partitioner builds the partitions (Section 3.1 asks for a graph
+ * partitioner minimising the entries that fall outside their row's
+ * partition). */
+typedef enum {
+    EHYB_PART_MULTILEVEL = 0, /* multilevel graph partitioner (default) */
+    EHYB_PART_NATURAL = 1     /* consecutive blocks of the given row order */
+} ehyb_partitioner;
+
+/* Input matrix in canonical CSR (host memory, borrowed for the call).
+ * n_rows == n_cols (the graph reading of Section 3.1 needs a square matrix:
+ * otherwise EHYB_EUNSUPPORTED).  row_ptr[0] == 0, row_ptr non-decreasing,
+ * row_ptr[n_rows] == nnz, columns strictly increasing within a row and in
+ * [0, n_cols) (otherwise EHYB_EINVAL).  Explicit zeros are kept bit for bit. */
+typedef struct {
+    int64_t n_rows, n_cols, nnz;
+    const int64_t *row_ptr;  /* [n_rows + 1] */
+    const int32_t *col_idx;  /* [nnz] */
+    const double *val;       /* [nnz] */
+} ehyb_csr_host;
+
+/* Preprocessing parameters; a zero field takes the stated default. */
+typedef struct {
+    int32_t slice_rows;     /* target rows per partition (x-slice length).
+                               0 = Eq. 1-2: smallest K with n*tau/(K*P) < lds_bytes,
+                               VecSize = ceil(n/(K*P)), floored at min(n, 512). */
+    int32_t ell_width_cap;  /* max ELL entries per row; 0 = unlimited (the
+                               paper's split by partition only) */
+    int32_t rows_per_wave;  /* rows per 64-lane wavefront row-slice, a power of
+                               two in [1, 64]; 64/rows_per_wave lanes share a
+                               row. 0 = 64 (one lane per row) */
+    int32_t value_dtype;    /* ehyb_dtype; 0 = EHYB_F64 */
+    int32_t lds_bytes;      /* x-slice budget per workgroup; 0 = 160 KiB */
+    int32_t num_cus;        /* P in Eq. 1; 0 = 256 */
+    int32_t n_threads;      /* host threads; 0 = all available */
+    int32_t imbalance_pct;  /* allowed overfill of a partition above
+                               slice_rows, percent; 0 = 3 */
+    int32_t partitioner;    /* ehyb_partitioner; 0 = multilevel */
+    int32_t reserved;       /* must be 0 */
+    uint64_t seed;          /* partitioner seed (deterministic for a seed) */
+} ehyb_params;
+
+typedef struct {
+    int64_t n, nnz;           /* matrix size and stored entries */
+    int64_t nnz_ell, nnz_er;  /* entries in the ELL part / residual part */
+    int64_t ell_slots;        /* ELL slots including padding */
+    int64_t er_slots;         /* residual slots including padding */
+    int64_t n_er_rows;        /* rows with at least one residual entry */
+    int64_t device_bytes;     /* size of the device blob for ehyb_plan_upload */
+    int64_t algorithmic_bytes;/* bytes one permuted-space SpMV must move, each
+                                 array element once: ELL and residual slots
+                                 (values + columns, padding included), slice
+                                 and partition metadata, x once, y once.  The
+                                 residual part's x gathers re-read x and are
+                                 not counted. */
+    int32_t nparts;           /* partitions (workgroup-sized x-slices) */
+    int32_t nslices;          /* row-slices (one wavefront task each) */
+    int32_t slice_rows;       /* target rows per partition actually used */
+    int32_t max_part_rows;    /* largest partition */
+    int32_t rows_per_slice;   /* C = rows_per_wave */
+    int32_t lanes_per_row;    /* L = 64 / C */
+    int32_t kc;               /* ELL entries per lane per load step */
+    int32_t value_dtype;      /* ehyb_dtype */
+    int32_t eq1_K;            /* K of Eq. 1 for this n (informational) */
+    int32_t reserved;
+    double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */
+} ehyb_plan_stats;
+
+/* Read-only views of a plan's host arrays (owned by the plan, valid until
+ * ehyb_plan_destroy).  Layout of the two parts, for row r (0 <= r < C) of
+ * row-slice s and its k-th entry in ascending permuted column order:
+ *   t = k / (L*KC), u = (k / KC) % L, c = k % KC, lane = r*L + u,
+ *   slot = off[s] + (t*64 + lane)*KC + c,
+ * with (off, steps) = slice_meta[4s+0], [4s+1] and KC = kc for the ELL part,
+ * slice_meta[4s+2], [4s+3] and KC = 1 for the residual part.  Each step of a
+ * row-slice holds 64*KC slots.  Row r of slice s is permuted row
+ * part_start[p] + (s - slice_start[p])*C + r for the partition p holding s.
+ * ELL columns are offsets from part_start[p]; residual columns are permuted
+ * global indices.  Padding slots hold +0.0 and column 0. */
+typedef struct {
+    int64_t n;
+    int32_t nparts, nslices, lanes_per_row, kc, value_dtype, reserved;
+    int64_t ell_slots, er_slots;
+    const int32_t *perm;        /* [n] new index -> original index */
+    const int32_t *part_start;  /* [nparts + 1] first permuted row of each partition */
+    const int32_t *slice_start; /* [nparts + 1] first row-slice of each partition */
+    const uint32_t *slice_meta; /* [4 * nslices] ell_off, ell_steps, er_off, er_steps */
+    const void *ell_val;        /* [ell_slots] values, value_dtype */
+    const uint16_t *ell_col;    /* [ell_slots] local columns */
+    const void *er_val;         /* [er_slots] values, value_dtype */
+    const int32_t *er_col;      /* [er_slots] permuted global columns */
+    const int32_t *row_ell_len; /* [n] ELL entries of each permuted row */
+    const int32_t *row_er_len;  /* [n] residual entries of each permuted row */
+} ehyb_plan_arrays;
+
+typedef struct ehyb_plan ehyb_plan;
+
+/* Flags of ehyb_spmv. */
+#define EHYB_VEC_PERMUTED 1u  /* x and y are in the plan's permuted order
+                                 (x_perm[i] = x[perm[i]]); otherwise they are in
+                                 the original order and the library permutes
+                                 through scratch space inside the device blob */
+
+/* Host preprocessing (Alg. 1 and Alg. 2): validate A, build its graph,
+ * partition it, reorder rows, and encode both parts.  Host only; `A` is
+ * borrowed for the call.  On success *out owns a new plan. */
+EHYB_API ehyb_status ehyb_preprocess(const ehyb_csr_host *A, const ehyb_params *params,
+                            ehyb_plan **out);
+
+/* Statistics of a plan. */
+EHYB_API ehyb_status ehyb_plan_stats_get(const ehyb_plan *plan, ehyb_plan_stats *out);
+
+/* Views of a plan's host arrays (see ehyb_plan_arrays). */
+EHYB_API ehyb_status ehyb_plan_arrays_get(const ehyb_plan *plan, ehyb_plan_arrays *out);
+
+/* Decode the plan back to CSR of P A P^T (B[i][j] = A[perm[i]][perm[j]]),
+ * columns ascending, values converted exactly to FP64 (bit-identical to A's
+ * for FP64 plans).  Host buffers of n+1, nnz and nnz elements. */
+EHYB_API ehyb_status ehyb_plan_decode_csr(const ehyb_plan *plan, int64_t *row_ptr, int32_t *col_idx,
+                                 double *val);
+
+/* Bytes of device memory the plan needs (metadata, both parts, permutation
+ * and two n-vectors of scratch for unpermuted calls), 256-byte aligned. */
+EHYB_API ehyb_status ehyb_plan_device_bytes(const ehyb_plan *plan, size_t *bytes);
+
+/* Copy the plan into `dev_blob` (device, at least device_bytes bytes,
+ * 256-byte aligned; owned by the caller, who keeps it alive and unmodified
+ * while any launch on it may run).  Waits for the copies to finish before
+ * returning.  Rebinding to another blob is allowed. */
+EHYB_API ehyb_status ehyb_plan_upload(ehyb_plan *plan, void *dev_blob, size_t bytes, void *stream);
+
+/* y = A x on the device (Alg. 3).  x, y: device FP64 vectors of length n for
+ * FP64 plans.  With EHYB_VEC_PERMUTED they are in permuted order; otherwise in
+ * the original order.  Launches on one plan blob must not overlap in time when
+ * the unpermuted mode is used (they share its scratch vectors).  Every row of
+ * y is overwritten; the result is bitwise deterministic. */
+EHYB_API ehyb_status ehyb_spmv(const ehyb_plan *plan, const void *x, void *y, uint32_t flags,
+                      void *stream);
+
+/* x_perm[i] = x[perm[i]] and y[perm[i]] = y_perm[i] on the device (the
+ * reordering applied to vectors; FP64 for FP64 plans). */
+EHYB_API ehyb_status ehyb_permute_x(const ehyb_plan *plan, const void *x, void *x_perm, void *stream);
+EHYB_API ehyb_status ehyb_unpermute_y(const ehyb_plan *plan, const void *y_perm, void *y, void *stream);
+
+/* Save / load a plan (host arrays only) as a versioned binary file with a
+ * checksum; a loaded plan must be uploaded before use.  A corrupted or
+ * truncated file gives EHYB_EINVAL. */
+EHYB_API ehyb_status ehyb_plan_save(const ehyb_plan *plan, const char *path);
+EHYB_API ehyb_status ehyb_plan_load(const char *path, ehyb_plan **out);
+
+EHYB_API void ehyb_plan_destroy(ehyb_plan *plan);
+
+/* Baseline: plain CSR y = A x on the device, FP64, one group of
+ * `lanes_per_row` lanes (power of two in [1, 64]; 0 = chosen from the mean row
+ * length) per row.  row_ptr int32 [n_rows+1], col int32 [nnz], val [nnz], x,
+ * y device.  The comparator of the method (CSR lineage, Section 2.2). */
+EHYB_API ehyb_status ehyb_csr_spmv_f64(int64_t n_rows, int64_t nnz, const int32_t *row_ptr,
+                              const int32_t *col_idx, const double *val, const double *x,
+                              double *y, int32_t lanes_per_row, void *stream);
+
+/* Bandwidth probes (the denominators of the HBM fraction).  read: streams
+ * `bytes` (multiple of 16) from `buf` with 16-byte loads and writes one
+ * 8-byte partial per workgroup to `sink` (device, >= 8 * 65536 bytes).
+ * copy: copies `bytes` (multiple of 16) from src to dst. */
+EHYB_API ehyb_status ehyb_probe_read(const void *buf, size_t bytes, void *sink, void *stream);
+EHYB_API ehyb_status ehyb_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
+
+typedef struct {
+    int32_t device, num_cus, lds_per_block, warp_size, clock_khz, mem_clock_khz;
+    int32_t mem_bus_width, l2_bytes;
+    char arch[64];
+} ehyb_device_info;
+
+/* Properties of the current device. */
+EHYB_API ehyb_status ehyb_device_info_get(ehyb_device_info *out);
+
+/* Message of the last failing call on this thread ("" if none). */
+EHYB_API const char *ehyb_last_error(void);
+
+/* Library version, e.g. "0.1.0". */
+EHYB_API const char *ehyb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EHYB_H */

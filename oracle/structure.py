@@ -173,7 +173,7 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
     for which, vals, cols in (("ell", ell_val, ell_col), ("er", er_val, er_col)):
         slot, row, k, valid, part = _slots(view, which)
         pad = slot[~valid]
-        bits = np.ascontiguousarray(vals[pad]).view(np.uint8).reshape(pad.size, -1)
+        bits = np.ascontiguousarray(vals[pad]).view(np.uint8)
         _req(not bits.any(), f"{which} padding slot is not +0.0")
         pc = cols[pad].astype(np.int64)
         if which == "ell":

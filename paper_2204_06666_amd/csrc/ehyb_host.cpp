@@ -1,0 +1,804 @@
+// Host side of the EHYB library: input validation, graph construction,
+// partitioning, reordering (Alg. 1), encoding of the two parts (Alg. 2),
+// decoding, plan views and plan files.  No device code lives here.
+#include <omp.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <numeric>
+#include <stdexcept>
+
+#include "internal.h"
+
+namespace ehyb {
+
+namespace {
+thread_local std::string g_last_error;
+
+double now_s() {
+    using clk = std::chrono::steady_clock;
+    return std::chrono::duration<double>(clk::now().time_since_epoch()).count();
+}
+
+int threads_for(const ehyb_params& p) {
+    return p.n_threads > 0 ? p.n_threads : omp_get_max_threads();
+}
+
+// Sets the OpenMP thread count for the library's own parallel regions and
+// restores the caller's setting on exit.
+struct ThreadGuard {
+    int prev;
+    explicit ThreadGuard(int n) : prev(omp_get_max_threads()) { omp_set_num_threads(n); }
+    ~ThreadGuard() { omp_set_num_threads(prev); }
+};
+
+// Round a binary64 value to the nearest bfloat16 (ties to even) without
+// passing through binary32, returning its 16-bit pattern.
+uint16_t double_to_bf16(double d) {
+    if (std::isnan(d)) return 0x7FC0;
+    if (d == 0.0) return std::signbit(d) ? 0x8000 : 0x0000;
+    const double a = std::fabs(d);
+    int e;
+    std::frexp(a, &e);                  // a = m * 2^e, m in [0.5, 1)
+    int ulp_exp = (e - 1) - 7;          // 8 significant bits
+    if (ulp_exp < -133) ulp_exp = -133;  // subnormal range of bfloat16
+    const double q = std::nearbyint(std::ldexp(a, -ulp_exp));  // ties to even
+    const double r = std::ldexp(q, ulp_exp);
+    float f = (r > 3.3895313892515355e38) ? INFINITY : (float)r;  // exact when finite
+    uint32_t bits;
+    std::memcpy(&bits, &f, 4);
+    uint16_t h = (uint16_t)(bits >> 16);
+    if (std::signbit(d)) h |= 0x8000;
+    return h;
+}
+
+void store_value(unsigned char* dst, int vbytes, int dtype, double v) {
+    if (dtype == EHYB_F64) {
+        std::memcpy(dst, &v, 8);
+    } else if (dtype == EHYB_F32) {
+        float f = (float)v;
+        std::memcpy(dst, &f, 4);
+    } else {
+        uint16_t h = double_to_bf16(v);
+        std::memcpy(dst, &h, 2);
+    }
+    (void)vbytes;
+}
+
+double load_value(const unsigned char* src, int dtype) {
+    if (dtype == EHYB_F64) {
+        double d;
+        std::memcpy(&d, src, 8);
+        return d;
+    }
+    if (dtype == EHYB_F32) {
+        float f;
+        std::memcpy(&f, src, 4);
+        return (double)f;
+    }
+    uint16_t h;
+    std::memcpy(&h, src, 2);
+    uint32_t bits = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &bits, 4);
+    return (double)f;
+}
+
+Error validate(const ehyb_csr_host* A) {
+    Error e;
+    auto bad = [&](ehyb_status st, std::string m) {
+        e.status = st;
+        e.msg = std::move(m);
+        return e;
+    };
+    if (A->n_rows < 0 || A->n_cols < 0 || A->nnz < 0) return bad(EHYB_EINVAL, "negative size");
+    if (A->n_rows != A->n_cols)
+        return bad(EHYB_EUNSUPPORTED, "matrix is not square (rows and columns are one vertex set)");
+    if (A->n_rows > (int64_t)INT32_MAX - 1) return bad(EHYB_EUNSUPPORTED, "more than 2^31-2 rows");
+    if (A->nnz > 0 && (!A->col_idx || !A->val)) return bad(EHYB_EINVAL, "null col_idx or val");
+    if (!A->row_ptr) return bad(EHYB_EINVAL, "null row_ptr");
+    const int64_t n = A->n_rows;
+    if (A->row_ptr[0] != 0) return bad(EHYB_EINVAL, "row_ptr[0] != 0");
+    if (A->row_ptr[n] != A->nnz) return bad(EHYB_EINVAL, "row_ptr[n] != nnz");
+    for (int64_t i = 0; i < n; ++i)
+        if (A->row_ptr[i + 1] < A->row_ptr[i])
+            return bad(EHYB_EINVAL, "row_ptr decreases at row " + std::to_string(i));
+    int64_t bad_row = -1;
+    int bad_kind = 0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t p = A->row_ptr[i]; p < A->row_ptr[i + 1]; ++p) {
+            const int32_t c = A->col_idx[p];
+            int kind = 0;
+            if (c < 0 || c >= n) kind = 1;
+            else if (p > A->row_ptr[i] && c <= A->col_idx[p - 1]) kind = 2;
+            if (kind) {
+#pragma omp critical
+                {
+                    if (bad_row < 0 || i < bad_row) {
+                        bad_row = i;
+                        bad_kind = kind;
+                    }
+                }
+                break;
+            }
+        }
+    }
+    if (bad_row >= 0)
+        return bad(EHYB_EINVAL, std::string(bad_kind == 1 ? "column index out of range"
+                                                          : "columns not strictly increasing (unsorted or duplicate)") +
+                                    " in row " + std::to_string(bad_row));
+    return e;
+}
+
+// Graph of A + A^T without self loops; edge weight = number of stored entries
+// among a_ij, a_ji (Section 3.1: each entry is an edge between its row and
+// column vertices).
+Graph build_graph(const ehyb_csr_host* A) {
+    const int32_t n = (int32_t)A->n_rows;
+    const int64_t nnz = A->nnz;
+    // transpose pattern (CSC): rows of each column, ascending
+    std::vector<int64_t> tptr(n + 1, 0);
+    for (int64_t p = 0; p < nnz; ++p) tptr[A->col_idx[p] + 1]++;
+    for (int32_t j = 0; j < n; ++j) tptr[j + 1] += tptr[j];
+    std::vector<int32_t> trow(nnz);
+    {
+        std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+        for (int32_t i = 0; i < n; ++i)
+            for (int64_t p = A->row_ptr[i]; p < A->row_ptr[i + 1]; ++p) trow[fill[A->col_idx[p]]++] = i;
+    }
+    Graph g;
+    g.n = n;
+    g.xadj.assign(n + 1, 0);
+    g.vw.assign(n, 1);
+    // union of row v's columns and column v's rows, self excluded
+    auto merge = [&](int32_t v, int32_t* adj, int32_t* ew) -> int64_t {
+        int64_t a = A->row_ptr[v], ae = A->row_ptr[v + 1];
+        int64_t b = tptr[v], be = tptr[v + 1];
+        int64_t k = 0;
+        while (a < ae || b < be) {
+            int32_t ca = a < ae ? A->col_idx[a] : INT32_MAX;
+            int32_t cb = b < be ? trow[b] : INT32_MAX;
+            int32_t c;
+            int32_t w;
+            if (ca == cb) {
+                c = ca;
+                w = 2;
+                ++a;
+                ++b;
+            } else if (ca < cb) {
+                c = ca;
+                w = 1;
+                ++a;
+            } else {
+                c = cb;
+                w = 1;
+                ++b;
+            }
+            if (c == v) continue;
+            if (adj) {
+                adj[k] = c;
+                ew[k] = w;
+            }
+            ++k;
+        }
+        return k;
+    };
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int32_t v = 0; v < n; ++v) g.xadj[v + 1] = merge(v, nullptr, nullptr);
+    for (int32_t v = 0; v < n; ++v) g.xadj[v + 1] += g.xadj[v];
+    g.adj.resize(g.xadj[n]);
+    g.ew.resize(g.xadj[n]);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int32_t v = 0; v < n; ++v) merge(v, g.adj.data() + g.xadj[v], g.ew.data() + g.xadj[v]);
+    return g;
+}
+
+}  // namespace
+
+ehyb_status fail(ehyb_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+ehyb_status ok() { return EHYB_OK; }
+
+int64_t algorithmic_bytes(const ehyb_plan& p) {
+    int64_t b = 0;
+    b += p.ell_slots * (p.vbytes + 2);                 // ELL values + 16-bit columns
+    b += p.er_slots * (p.vbytes + 4);                  // residual values + 32-bit columns
+    b += (int64_t)p.nslices * 16;                      // row-slice metadata
+    b += (int64_t)(p.nparts + 1) * 8;                  // partition + slice boundaries
+    b += p.n * p.xbytes;                               // x, each element once (slice staging)
+    b += p.n * p.xbytes;                               // y, written once
+    return b;
+}
+
+BlobLayout compute_layout(const ehyb_plan& p) {
+    BlobLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += (bytes + kBlobAlign - 1) / kBlobAlign * kBlobAlign;
+        return at;
+    };
+    L.part_start = take((size_t)(p.nparts + 1) * 4);
+    L.slice_start = take((size_t)(p.nparts + 1) * 4);
+    L.slice_meta = take((size_t)p.nslices * 16);
+    L.ell_val = take((size_t)p.ell_slots * p.vbytes);
+    L.ell_col = take((size_t)p.ell_slots * 2);
+    L.er_val = take((size_t)p.er_slots * p.vbytes);
+    L.er_col = take((size_t)p.er_slots * 4);
+    L.perm = take((size_t)p.n * 4);
+    L.xp = take((size_t)p.n * p.xbytes);
+    L.yp = take((size_t)p.n * p.xbytes);
+    L.total = off == 0 ? kBlobAlign : off;
+    return L;
+}
+
+}  // namespace ehyb
+
+using namespace ehyb;
+
+namespace {
+
+// Alg. 1 (classification and reordering) and Alg. 2 (moving entries into the
+// ELL and residual parts), given the partition vector.
+ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part, int32_t nparts,
+                       ehyb_plan* P) {
+    const int32_t n = (int32_t)A->n_rows;
+    const int cap = P->params.ell_width_cap;
+    const int L = P->L, C = P->C, kc = P->kc;
+    double t0 = now_s();
+
+    // Alg. 1: in-partition (ELL) and other (residual) entry counts per row
+    std::vector<int32_t> ell_cnt(n), er_cnt(n);
+#pragma omp parallel for schedule(static)
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t in = 0;
+        for (int64_t p = A->row_ptr[i]; p < A->row_ptr[i + 1]; ++p)
+            if (part[A->col_idx[p]] == part[i]) ++in;
+        const int32_t len = (int32_t)(A->row_ptr[i + 1] - A->row_ptr[i]);
+        ell_cnt[i] = (cap > 0 && in > cap) ? cap : in;
+        er_cnt[i] = len - ell_cnt[i];
+    }
+    // rows grouped by partition (stable in the original index), then each
+    // partition sorted by non-increasing ELL count (stable)
+    P->part_start.assign(nparts + 1, 0);
+    for (int32_t i = 0; i < n; ++i) P->part_start[part[i] + 1]++;
+    for (int32_t p = 0; p < nparts; ++p) P->part_start[p + 1] += P->part_start[p];
+    P->perm.resize(n);
+    {
+        std::vector<int32_t> fill(P->part_start.begin(), P->part_start.end() - 1);
+        for (int32_t i = 0; i < n; ++i) P->perm[fill[part[i]]++] = i;
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t p = 0; p < nparts; ++p)
+        std::stable_sort(P->perm.begin() + P->part_start[p], P->perm.begin() + P->part_start[p + 1],
+                         [&](int32_t a, int32_t b) { return ell_cnt[a] > ell_cnt[b]; });
+    P->iperm.resize(n);
+    for (int32_t i = 0; i < n; ++i) P->iperm[P->perm[i]] = i;
+    P->row_ell_len.resize(n);
+    P->row_er_len.resize(n);
+    int32_t maxp = 0;
+    for (int32_t p = 0; p < nparts; ++p) maxp = std::max(maxp, P->part_start[p + 1] - P->part_start[p]);
+    P->max_part_rows = maxp;
+    for (int32_t i = 0; i < n; ++i) {
+        P->row_ell_len[i] = ell_cnt[P->perm[i]];
+        P->row_er_len[i] = er_cnt[P->perm[i]];
+    }
+    P->t_reorder = now_s() - t0;
+    t0 = now_s();
+
+    // row-slices: C consecutive rows of one partition; widths and offsets
+    P->slice_start.assign(nparts + 1, 0);
+    for (int32_t p = 0; p < nparts; ++p)
+        P->slice_start[p + 1] = P->slice_start[p] + (P->part_start[p + 1] - P->part_start[p] + C - 1) / C;
+    const int32_t ns = P->slice_start[nparts];
+    P->nslices = ns;
+    P->nparts = nparts;
+    std::vector<int32_t> slice_part(ns);
+    for (int32_t p = 0; p < nparts; ++p)
+        for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) slice_part[s] = p;
+    std::vector<int64_t> ell_steps(ns), er_steps(ns);
+#pragma omp parallel for schedule(static)
+    for (int32_t s = 0; s < ns; ++s) {
+        const int32_t p = slice_part[s];
+        const int32_t r0 = P->part_start[p] + (s - P->slice_start[p]) * C;
+        const int32_t r1 = std::min(r0 + C, P->part_start[p + 1]);
+        int32_t me = 0, mr = 0;
+        for (int32_t r = r0; r < r1; ++r) {
+            me = std::max(me, P->row_ell_len[r]);
+            mr = std::max(mr, P->row_er_len[r]);
+        }
+        ell_steps[s] = (me + L * kc - 1) / (L * kc);
+        er_steps[s] = (mr + L - 1) / L;
+    }
+    P->slice_meta.assign((size_t)ns * 4, 0);
+    int64_t eoff = 0, roff = 0;
+    for (int32_t s = 0; s < ns; ++s) {
+        if (eoff > UINT32_MAX || roff > UINT32_MAX || ell_steps[s] > UINT32_MAX)
+            return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in one part");
+        P->slice_meta[4 * s + 0] = (uint32_t)eoff;
+        P->slice_meta[4 * s + 1] = (uint32_t)ell_steps[s];
+        P->slice_meta[4 * s + 2] = (uint32_t)roff;
+        P->slice_meta[4 * s + 3] = (uint32_t)er_steps[s];
+        eoff += ell_steps[s] * kWave * kc;
+        roff += er_steps[s] * kWave;
+    }
+    if (eoff > UINT32_MAX || roff > UINT32_MAX)
+        return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in one part");
+    P->ell_slots = eoff;
+    P->er_slots = roff;
+    const int vb = P->vbytes, dt = P->value_dtype;
+    P->ell_val.assign((size_t)eoff * vb, 0);   // +0.0 padding in every value type
+    P->ell_col.assign((size_t)eoff, 0);
+    P->er_val.assign((size_t)roff * vb, 0);
+    P->er_col.assign((size_t)roff, 0);
+
+    // Alg. 2: move each entry, with its column renumbered by the reorder
+    // table, into its slot
+    int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0;
+#pragma omp parallel reduction(+ : nnz_ell, nnz_er, n_er_rows)
+    {
+        std::vector<std::pair<int32_t, int64_t>> ent;  // (new column, source position)
+#pragma omp for schedule(dynamic, 64)
+        for (int32_t s = 0; s < ns; ++s) {
+            const int32_t p = slice_part[s];
+            const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
+            const int32_t r0 = ps + (s - P->slice_start[p]) * C;
+            const int32_t r1 = std::min(r0 + C, pe);
+            const int64_t eo = P->slice_meta[4 * s + 0], ro = P->slice_meta[4 * s + 2];
+            for (int32_t row = r0; row < r1; ++row) {
+                const int32_t r = row - r0;
+                const int32_t old = P->perm[row];
+                ent.clear();
+                for (int64_t q = A->row_ptr[old]; q < A->row_ptr[old + 1]; ++q)
+                    ent.emplace_back(P->iperm[A->col_idx[q]], q);
+                std::sort(ent.begin(), ent.end());
+                int32_t k1 = 0, k2 = 0;
+                const int32_t ell_len = P->row_ell_len[row];
+                for (const auto& pr : ent) {
+                    const int32_t nc = pr.first;
+                    const double v = A->val[pr.second];
+                    if (nc >= ps && nc < pe && k1 < ell_len) {
+                        const int32_t k = k1++;
+                        const int64_t t = k / (L * kc), u = (k / kc) % L, c = k % kc;
+                        const int64_t slot = eo + (t * kWave + r * L + u) * kc + c;
+                        store_value(&P->ell_val[(size_t)slot * vb], vb, dt, v);
+                        P->ell_col[slot] = (uint16_t)(nc - ps);
+                    } else {
+                        const int32_t k = k2++;
+                        const int64_t t = k / L, u = k % L;
+                        const int64_t slot = ro + t * kWave + r * L + u;
+                        store_value(&P->er_val[(size_t)slot * vb], vb, dt, v);
+                        P->er_col[slot] = nc;
+                    }
+                }
+                nnz_ell += k1;
+                nnz_er += k2;
+                n_er_rows += k2 > 0;
+            }
+        }
+    }
+    P->nnz_ell = nnz_ell;
+    P->nnz_er = nnz_er;
+    P->n_er_rows = n_er_rows;
+    P->t_encode = now_s() - t0;
+    return EHYB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ehyb_last_error(void) { return g_last_error.c_str(); }
+
+const char* ehyb_version(void) { return "0.1.0"; }
+
+ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, ehyb_plan** out) {
+    try {
+        g_last_error.clear();
+        if (!A || !out) return fail(EHYB_EINVAL, "null argument");
+        *out = nullptr;
+        ehyb_params prm{};
+        if (params) prm = *params;
+        Error e = validate(A);
+        if (!e.ok()) return fail(e.status, e.msg);
+        if (prm.reserved != 0) return fail(EHYB_EINVAL, "reserved parameter field must be 0");
+        if (prm.value_dtype < 0 || prm.value_dtype > 2) return fail(EHYB_EINVAL, "unknown value dtype");
+        if (prm.rows_per_wave == 0) prm.rows_per_wave = kWave;
+        if (prm.rows_per_wave < 1 || prm.rows_per_wave > kWave ||
+            (prm.rows_per_wave & (prm.rows_per_wave - 1)))
+            return fail(EHYB_EINVAL, "rows_per_wave must be a power of two in [1, 64]");
+        if (prm.lds_bytes == 0) prm.lds_bytes = 160 * 1024;
+        if (prm.lds_bytes < 64 || prm.lds_bytes > 160 * 1024)
+            return fail(EHYB_EINVAL, "lds_bytes must be in [64, 163840]");
+        if (prm.num_cus == 0) prm.num_cus = 256;
+        if (prm.num_cus < 1) return fail(EHYB_EINVAL, "num_cus must be positive");
+        if (prm.imbalance_pct == 0) prm.imbalance_pct = 3;
+        if (prm.imbalance_pct < 0 || prm.imbalance_pct > 100)
+            return fail(EHYB_EINVAL, "imbalance_pct must be in [0, 100]");
+        if (prm.ell_width_cap < 0) return fail(EHYB_EINVAL, "ell_width_cap must be >= 0");
+        if (prm.partitioner < 0 || prm.partitioner > 1) return fail(EHYB_EINVAL, "unknown partitioner");
+        if (prm.n_threads < 0) return fail(EHYB_EINVAL, "n_threads must be >= 0");
+
+        auto P = std::unique_ptr<ehyb_plan>(new ehyb_plan());
+        const int64_t n = A->n_rows;
+        P->n = n;
+        P->nnz = A->nnz;
+        P->value_dtype = prm.value_dtype;
+        P->vbytes = prm.value_dtype == EHYB_F64 ? 8 : (prm.value_dtype == EHYB_F32 ? 4 : 2);
+        P->xbytes = prm.value_dtype == EHYB_F64 ? 8 : 4;
+        P->C = prm.rows_per_wave;
+        P->L = kWave / prm.rows_per_wave;
+        P->kc = kEllKC;
+        const int64_t max_rows = std::min<int64_t>(65536, prm.lds_bytes / P->xbytes);
+        if (max_rows < 1) return fail(EHYB_EINVAL, "lds_bytes smaller than one x element");
+        // Eq. 1-2: smallest K with n*tau/(K*P) < SHM, VecSize = ceil(n/(K*P))
+        int64_t K = 1;
+        while (n * P->xbytes >= (int64_t)prm.lds_bytes * K * prm.num_cus) ++K;
+        P->eq1_K = (int32_t)K;
+        const int64_t vec = n > 0 ? (n + K * prm.num_cus - 1) / (K * prm.num_cus) : 0;
+        if (prm.slice_rows == 0)
+            prm.slice_rows = (int32_t)std::max<int64_t>(
+                1, std::min<int64_t>(max_rows, std::max<int64_t>(vec, std::min<int64_t>(n, 512))));
+        if (prm.slice_rows < 1) return fail(EHYB_EINVAL, "slice_rows must be >= 1");
+        if (prm.slice_rows > max_rows)
+            return fail(EHYB_EINVAL, "slice_rows x-slice exceeds the LDS budget or 2^16 rows");
+        const int64_t cap = std::min<int64_t>(max_rows, prm.slice_rows + (int64_t)prm.slice_rows * prm.imbalance_pct / 100);
+        const int32_t nparts_req = n > 0 ? (int32_t)((n + prm.slice_rows - 1) / prm.slice_rows) : 0;
+        P->params = prm;
+        ThreadGuard tg(threads_for(prm));
+
+        std::vector<int32_t> part;
+        int32_t nparts = nparts_req;
+        double t0 = now_s();
+        if (prm.partitioner == EHYB_PART_NATURAL || nparts_req <= 1) {
+            part.resize(n);
+            for (int64_t i = 0; i < n; ++i) part[i] = (int32_t)(i / prm.slice_rows);
+            P->t_graph = 0;
+            P->t_partition = now_s() - t0;
+        } else {
+            Graph g = build_graph(A);
+            P->t_graph = now_s() - t0;
+            t0 = now_s();
+            Error pe = partition_multilevel(g, nparts_req, cap, prm.seed, part, nparts);
+            if (!pe.ok()) return fail(pe.status, pe.msg);
+            P->t_partition = now_s() - t0;
+        }
+        ehyb_status st = build_plan(A, part, nparts, P.get());
+        if (st != EHYB_OK) return st;
+        *out = P.release();
+        return EHYB_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(EHYB_ENOMEM, "host allocation failed during preprocessing");
+    } catch (const std::exception& ex) {
+        return fail(EHYB_EINVAL, std::string("preprocessing failed: ") + ex.what());
+    }
+}
+
+ehyb_status ehyb_plan_stats_get(const ehyb_plan* P, ehyb_plan_stats* out) {
+    if (!P || !out) return fail(EHYB_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->n = P->n;
+    out->nnz = P->nnz;
+    out->nnz_ell = P->nnz_ell;
+    out->nnz_er = P->nnz_er;
+    out->ell_slots = P->ell_slots;
+    out->er_slots = P->er_slots;
+    out->n_er_rows = P->n_er_rows;
+    out->device_bytes = (int64_t)compute_layout(*P).total;
+    out->algorithmic_bytes = algorithmic_bytes(*P);
+    out->nparts = P->nparts;
+    out->nslices = P->nslices;
+    out->slice_rows = P->params.slice_rows;
+    out->max_part_rows = P->max_part_rows;
+    out->rows_per_slice = P->C;
+    out->lanes_per_row = P->L;
+    out->kc = P->kc;
+    out->value_dtype = P->value_dtype;
+    out->eq1_K = P->eq1_K;
+    out->t_graph_s = P->t_graph;
+    out->t_partition_s = P->t_partition;
+    out->t_reorder_s = P->t_reorder;
+    out->t_encode_s = P->t_encode;
+    return EHYB_OK;
+}
+
+ehyb_status ehyb_plan_arrays_get(const ehyb_plan* P, ehyb_plan_arrays* out) {
+    if (!P || !out) return fail(EHYB_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->n = P->n;
+    out->nparts = P->nparts;
+    out->nslices = P->nslices;
+    out->lanes_per_row = P->L;
+    out->kc = P->kc;
+    out->value_dtype = P->value_dtype;
+    out->ell_slots = P->ell_slots;
+    out->er_slots = P->er_slots;
+    out->perm = P->perm.data();
+    out->part_start = P->part_start.data();
+    out->slice_start = P->slice_start.data();
+    out->slice_meta = P->slice_meta.data();
+    out->ell_val = P->ell_val.data();
+    out->ell_col = P->ell_col.data();
+    out->er_val = P->er_val.data();
+    out->er_col = P->er_col.data();
+    out->row_ell_len = P->row_ell_len.data();
+    out->row_er_len = P->row_er_len.data();
+    return EHYB_OK;
+}
+
+ehyb_status ehyb_plan_decode_csr(const ehyb_plan* P, int64_t* row_ptr, int32_t* col_idx, double* val) {
+    if (!P || !row_ptr || (P->nnz > 0 && (!col_idx || !val))) return fail(EHYB_EINVAL, "null argument");
+    const int32_t n = (int32_t)P->n;
+    const int L = P->L, C = P->C, kc = P->kc, vb = P->vbytes, dt = P->value_dtype;
+    row_ptr[0] = 0;
+    for (int32_t i = 0; i < n; ++i) row_ptr[i + 1] = row_ptr[i] + P->row_ell_len[i] + P->row_er_len[i];
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int32_t p = 0; p < P->nparts; ++p) {
+        const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
+        for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
+            const int64_t eo = P->slice_meta[4 * s + 0], ro = P->slice_meta[4 * s + 2];
+            const int32_t r0 = ps + (s - P->slice_start[p]) * C;
+            for (int32_t r = 0; r < C && r0 + r < pe; ++r) {
+                const int32_t row = r0 + r;
+                int64_t out_at = row_ptr[row];
+                int32_t a = 0, b = 0;
+                const int32_t na = P->row_ell_len[row], nb = P->row_er_len[row];
+                auto ell_slot = [&](int32_t k) {
+                    const int64_t t = k / (L * kc), u = (k / kc) % L, c = k % kc;
+                    return eo + (t * kWave + r * L + u) * kc + c;
+                };
+                auto er_slot = [&](int32_t k) {
+                    const int64_t t = k / L, u = k % L;
+                    return ro + t * kWave + r * L + u;
+                };
+                while (a < na || b < nb) {
+                    const int32_t ca = a < na ? ps + P->ell_col[ell_slot(a)] : INT32_MAX;
+                    const int32_t cb = b < nb ? P->er_col[er_slot(b)] : INT32_MAX;
+                    if (ca < cb) {
+                        col_idx[out_at] = ca;
+                        val[out_at] = load_value(&P->ell_val[(size_t)ell_slot(a) * vb], dt);
+                        ++a;
+                    } else {
+                        col_idx[out_at] = cb;
+                        val[out_at] = load_value(&P->er_val[(size_t)er_slot(b) * vb], dt);
+                        ++b;
+                    }
+                    ++out_at;
+                }
+            }
+        }
+    }
+    return EHYB_OK;
+}
+
+ehyb_status ehyb_plan_device_bytes(const ehyb_plan* P, size_t* bytes) {
+    if (!P || !bytes) return fail(EHYB_EINVAL, "null argument");
+    *bytes = compute_layout(*P).total;
+    return EHYB_OK;
+}
+
+void ehyb_plan_destroy(ehyb_plan* P) { delete P; }
+
+}  // extern "C"
+
+// ------------------------------------------------------------- plan files
+// Layout: magic "EHYBPLN1", u32 version, then fixed header fields and arrays
+// (each prefixed by its u64 byte length), then a u64 FNV-1a checksum of all
+// preceding bytes.
+
+namespace {
+const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '1'};
+const uint32_t kVersion = 1;
+
+uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+struct Writer {
+    std::vector<unsigned char> buf;
+    void raw(const void* p, size_t n) {
+        const unsigned char* c = (const unsigned char*)p;
+        buf.insert(buf.end(), c, c + n);
+    }
+    template <class T> void pod(const T& v) { raw(&v, sizeof(T)); }
+    template <class T> void vec(const std::vector<T>& v) {
+        uint64_t b = v.size() * sizeof(T);
+        pod(b);
+        raw(v.data(), b);
+    }
+};
+
+struct Reader {
+    const unsigned char* p;
+    size_t n, at = 0;
+    bool ok = true;
+    void raw(void* d, size_t k) {
+        if (!ok || at + k > n) {
+            ok = false;
+            return;
+        }
+        std::memcpy(d, p + at, k);
+        at += k;
+    }
+    template <class T> void pod(T& v) { raw(&v, sizeof(T)); }
+    template <class T> void vec(std::vector<T>& v, uint64_t max_elems) {
+        uint64_t b = 0;
+        pod(b);
+        if (!ok || b % sizeof(T) || b / sizeof(T) > max_elems || at + b > n) {
+            ok = false;
+            return;
+        }
+        v.resize(b / sizeof(T));
+        raw(v.data(), b);
+    }
+};
+}  // namespace
+
+extern "C" {
+
+ehyb_status ehyb_plan_save(const ehyb_plan* P, const char* path) {
+    try {
+        if (!P || !path) return fail(EHYB_EINVAL, "null argument");
+        Writer w;
+        w.raw(kMagic, 8);
+        w.pod(kVersion);
+        w.pod(P->n);
+        w.pod(P->nnz);
+        w.pod(P->params);
+        w.pod(P->L);
+        w.pod(P->C);
+        w.pod(P->kc);
+        w.pod(P->nparts);
+        w.pod(P->nslices);
+        w.pod(P->value_dtype);
+        w.pod(P->eq1_K);
+        w.pod(P->max_part_rows);
+        w.pod(P->ell_slots);
+        w.pod(P->er_slots);
+        w.pod(P->nnz_ell);
+        w.pod(P->nnz_er);
+        w.pod(P->n_er_rows);
+        w.vec(P->perm);
+        w.vec(P->part_start);
+        w.vec(P->slice_start);
+        w.vec(P->slice_meta);
+        w.vec(P->ell_val);
+        w.vec(P->ell_col);
+        w.vec(P->er_val);
+        w.vec(P->er_col);
+        w.vec(P->row_ell_len);
+        w.vec(P->row_er_len);
+        uint64_t h = fnv1a(w.buf.data(), w.buf.size());
+        w.pod(h);
+        FILE* f = std::fopen(path, "wb");
+        if (!f) return fail(EHYB_EINVAL, std::string("cannot open ") + path + " for writing");
+        size_t wr = std::fwrite(w.buf.data(), 1, w.buf.size(), f);
+        int cl = std::fclose(f);
+        if (wr != w.buf.size() || cl != 0) return fail(EHYB_EINVAL, "short write to plan file");
+        return EHYB_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(EHYB_ENOMEM, "host allocation failed while saving");
+    }
+}
+
+ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
+    try {
+        if (!path || !out) return fail(EHYB_EINVAL, "null argument");
+        *out = nullptr;
+        FILE* f = std::fopen(path, "rb");
+        if (!f) return fail(EHYB_EINVAL, std::string("cannot open ") + path);
+        std::vector<unsigned char> buf;
+        unsigned char tmp[1 << 16];
+        size_t k;
+        while ((k = std::fread(tmp, 1, sizeof(tmp), f)) > 0) buf.insert(buf.end(), tmp, tmp + k);
+        std::fclose(f);
+        if (buf.size() < 8 + 4 + 8) return fail(EHYB_EINVAL, "plan file truncated");
+        uint64_t h;
+        std::memcpy(&h, buf.data() + buf.size() - 8, 8);
+        if (fnv1a(buf.data(), buf.size() - 8) != h) return fail(EHYB_EINVAL, "plan file checksum mismatch");
+        Reader r{buf.data(), buf.size() - 8};
+        char magic[8];
+        uint32_t ver = 0;
+        r.raw(magic, 8);
+        r.pod(ver);
+        if (!r.ok || std::memcmp(magic, kMagic, 8) != 0) return fail(EHYB_EINVAL, "not a plan file");
+        if (ver != kVersion) return fail(EHYB_EINVAL, "unsupported plan file version");
+        auto P = std::unique_ptr<ehyb_plan>(new ehyb_plan());
+        r.pod(P->n);
+        r.pod(P->nnz);
+        r.pod(P->params);
+        r.pod(P->L);
+        r.pod(P->C);
+        r.pod(P->kc);
+        r.pod(P->nparts);
+        r.pod(P->nslices);
+        r.pod(P->value_dtype);
+        r.pod(P->eq1_K);
+        r.pod(P->max_part_rows);
+        r.pod(P->ell_slots);
+        r.pod(P->er_slots);
+        r.pod(P->nnz_ell);
+        r.pod(P->nnz_er);
+        r.pod(P->n_er_rows);
+        if (!r.ok || P->n < 0 || P->n > INT32_MAX || P->nparts < 0 || P->nslices < 0 ||
+            P->value_dtype < 0 || P->value_dtype > 2 || P->L < 1 || P->L > kWave || P->C * P->L != kWave ||
+            P->kc != kEllKC || P->ell_slots < 0 || P->er_slots < 0)
+            return fail(EHYB_EINVAL, "plan file header is inconsistent");
+        P->vbytes = P->value_dtype == EHYB_F64 ? 8 : (P->value_dtype == EHYB_F32 ? 4 : 2);
+        P->xbytes = P->value_dtype == EHYB_F64 ? 8 : 4;
+        const uint64_t lim = (uint64_t)buf.size();
+        r.vec(P->perm, lim);
+        r.vec(P->part_start, lim);
+        r.vec(P->slice_start, lim);
+        r.vec(P->slice_meta, lim);
+        r.vec(P->ell_val, lim);
+        r.vec(P->ell_col, lim);
+        r.vec(P->er_val, lim);
+        r.vec(P->er_col, lim);
+        r.vec(P->row_ell_len, lim);
+        r.vec(P->row_er_len, lim);
+        if (!r.ok || r.at != r.n) return fail(EHYB_EINVAL, "plan file body is malformed");
+        const size_t n = (size_t)P->n;
+        if (P->perm.size() != n || P->part_start.size() != (size_t)P->nparts + 1 ||
+            P->slice_start.size() != (size_t)P->nparts + 1 || P->slice_meta.size() != (size_t)P->nslices * 4 ||
+            P->ell_val.size() != (size_t)P->ell_slots * P->vbytes || P->ell_col.size() != (size_t)P->ell_slots ||
+            P->er_val.size() != (size_t)P->er_slots * P->vbytes || P->er_col.size() != (size_t)P->er_slots ||
+            P->row_ell_len.size() != n || P->row_er_len.size() != n)
+            return fail(EHYB_EINVAL, "plan file array sizes are inconsistent");
+        // bounds that the kernels rely on
+        if (P->nparts > 0 && (P->part_start[0] != 0 || P->part_start[P->nparts] != (int32_t)n ||
+                              P->slice_start[0] != 0 || P->slice_start[P->nparts] != P->nslices))
+            return fail(EHYB_EINVAL, "plan file partition bounds are inconsistent");
+        for (int32_t p = 0; p < P->nparts; ++p) {
+            const int64_t sz = (int64_t)P->part_start[p + 1] - P->part_start[p];
+            const int64_t sl = (int64_t)P->slice_start[p + 1] - P->slice_start[p];
+            if (sz <= 0 || sz > 65536 || sz * P->xbytes > 160 * 1024 || sl != (sz + P->C - 1) / P->C)
+                return fail(EHYB_EINVAL, "plan file partition sizes are inconsistent");
+            for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
+                const uint64_t eo = P->slice_meta[4 * s], es = P->slice_meta[4 * s + 1];
+                const uint64_t ro = P->slice_meta[4 * s + 2], rs = P->slice_meta[4 * s + 3];
+                if (eo + es * kWave * P->kc > (uint64_t)P->ell_slots || ro + rs * kWave > (uint64_t)P->er_slots)
+                    return fail(EHYB_EINVAL, "plan file slot ranges are out of bounds");
+            }
+        }
+        // every stored column must be valid for the kernels' gathers
+        for (size_t s = 0; s < P->er_col.size(); ++s)
+            if (P->er_col[s] < 0 || (size_t)P->er_col[s] >= n)
+                return fail(EHYB_EINVAL, "plan file residual column out of range");
+        std::vector<char> seen(n, 0);
+        for (size_t i = 0; i < n; ++i) {
+            const int32_t o = P->perm[i];
+            if (o < 0 || (size_t)o >= n || seen[o]) return fail(EHYB_EINVAL, "plan file permutation is invalid");
+            seen[o] = 1;
+        }
+        P->iperm.resize(n);
+        for (size_t i = 0; i < n; ++i) P->iperm[P->perm[i]] = (int32_t)i;
+        for (int32_t p = 0; p < P->nparts; ++p) {
+            const int32_t sz = P->part_start[p + 1] - P->part_start[p];
+            for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
+                const uint64_t eo = P->slice_meta[4 * s], es = P->slice_meta[4 * s + 1];
+                for (uint64_t q = eo; q < eo + es * kWave * P->kc; ++q)
+                    if (P->ell_col[q] >= sz) return fail(EHYB_EINVAL, "plan file ELL column outside its slice");
+            }
+        }
+        *out = P.release();
+        return EHYB_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(EHYB_ENOMEM, "host allocation failed while loading");
+    }
+}
+
+}  // extern "C"

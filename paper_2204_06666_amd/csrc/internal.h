@@ -1,0 +1,84 @@
+// Internal definitions shared by the host preprocessing (C++) and the device
+// launch code (HIP).  Not part of the public ABI.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "ehyb.h"
+
+namespace ehyb {
+
+constexpr int kWave = 64;              // gfx950 wavefront width
+constexpr int kEllKC = 2;              // ELL entries per lane per load step
+constexpr size_t kBlobAlign = 256;
+
+// Undirected graph in CSR form with vertex and edge weights.
+struct Graph {
+    int32_t n = 0;
+    std::vector<int64_t> xadj;   // [n+1]
+    std::vector<int32_t> adj;    // [xadj[n]]
+    std::vector<int32_t> ew;     // edge weights, parallel to adj
+    std::vector<int32_t> vw;     // vertex weights [n]
+    int64_t total_vw() const;
+};
+
+// Sets err and returns a status.
+struct Error {
+    ehyb_status status = EHYB_OK;
+    std::string msg;
+    bool ok() const { return status == EHYB_OK; }
+};
+
+// Multilevel k-way graph partitioning with a hard cap on part weight.
+// part[v] in [0, nparts_out); every part non-empty and of weight <= cap.
+Error partition_multilevel(const Graph& g, int32_t nparts, int64_t cap, uint64_t seed,
+                           std::vector<int32_t>& part, int32_t& nparts_out);
+
+// Byte offsets of each array inside the device blob.
+struct BlobLayout {
+    size_t part_start = 0, slice_start = 0, slice_meta = 0;
+    size_t ell_val = 0, ell_col = 0, er_val = 0, er_col = 0;
+    size_t perm = 0, xp = 0, yp = 0;
+    size_t total = 0;
+};
+
+}  // namespace ehyb
+
+struct ehyb_plan {
+    int64_t n = 0, nnz = 0;
+    ehyb_params params{};          // resolved parameters
+    int32_t L = 1, C = 64, kc = ehyb::kEllKC;
+    int32_t nparts = 0, nslices = 0;
+    int32_t value_dtype = EHYB_F64;
+    int32_t vbytes = 8;            // bytes per stored value
+    int32_t xbytes = 8;            // bytes per x element
+    int32_t eq1_K = 1;
+    int32_t max_part_rows = 0;
+    std::vector<int32_t> perm;         // new -> old
+    std::vector<int32_t> iperm;        // old -> new (the reorder table)
+    std::vector<int32_t> part_start;   // [nparts+1]
+    std::vector<int32_t> slice_start;  // [nparts+1]
+    std::vector<uint32_t> slice_meta;  // [4*nslices]
+    std::vector<unsigned char> ell_val;  // ell_slots * vbytes
+    std::vector<uint16_t> ell_col;       // ell_slots
+    std::vector<unsigned char> er_val;   // er_slots * vbytes
+    std::vector<int32_t> er_col;         // er_slots
+    std::vector<int32_t> row_ell_len, row_er_len;  // [n], permuted rows
+    int64_t ell_slots = 0, er_slots = 0;
+    int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0;
+    double t_graph = 0, t_partition = 0, t_reorder = 0, t_encode = 0;
+    // device binding (non-owning)
+    void* dev_blob = nullptr;
+    size_t dev_bytes = 0;
+    ehyb::BlobLayout layout;
+};
+
+namespace ehyb {
+// Set the thread-local error message and return the status.
+ehyb_status fail(ehyb_status st, const std::string& msg);
+ehyb_status ok();
+BlobLayout compute_layout(const ehyb_plan& p);
+int64_t algorithmic_bytes(const ehyb_plan& p);
+}  // namespace ehyb

@@ -1,0 +1,232 @@
+"""Host preprocessing (Alg. 1-2) through the C ABI, checked on the CPU against
+the oracle: structure (O3), bit-exact round trip to P A P^T (O2), the layout
+interpreter against O1, error paths, plan files, determinism."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import matgen
+import oracle
+from oracle.structure import check_plan, layout_spmv
+from paper_2204_06666_amd import EhybError, Plan, _abi
+
+
+def _full_check(A, plan, value_dtype=np.float64, width_cap=0, x_seed=7, tau_x=8):
+    v = plan.arrays()
+    st = check_plan(A, v, width_cap=width_cap, value_dtype=value_dtype, tau_x=tau_x)
+    perm = v["perm"]
+    # decode == P A P^T, values bit for bit
+    rp, ci, val = plan.decode()
+    B = oracle.permute(A, perm)
+    assert np.array_equal(rp, B.row_ptr) and np.array_equal(ci, B.col)
+    want = B.val.astype(value_dtype).astype(np.float64)
+    assert np.array_equal(val.view(np.uint64), want.view(np.uint64))
+    if value_dtype == np.float64:
+        x = matgen.uniform_vector(A.n_rows, x_seed)
+        yp = layout_spmv(v, x[perm])
+        oracle.assert_close(yp, oracle.spmv(A, x)[perm], oracle.abs_scale(A, x)[perm], what="layout")
+    return st
+
+
+CASES = [
+    ("cfg1", lambda: matgen.config_matrix(1), {}),
+    ("cfg1-rowonly", lambda: matgen.poisson2d(64, perm_seed=1000, row_only=True), {}),
+    ("stencil27", lambda: matgen.stencil3d(18, perm_seed=3, val_seed=4), {"slice_rows": 700}),
+    ("stencil7-natural", lambda: matgen.stencil3d(16, points=7, perm_seed=5, val_seed=6),
+     {"slice_rows": 300, "partitioner": 1}),
+    ("knn", lambda: matgen.knn_fem(1500, perm_seed=1, pt_seed=2, val_seed=3), {"slice_rows": 1024}),
+    ("powerlaw", lambda: matgen.powerlaw(3000, exponent=2.3, mean_deg=12, seed=9), {"slice_rows": 400}),
+    ("edge-small", lambda: matgen.random_small(200, 0.05, 8, empty_rows=20, dense_row=True,
+                                               explicit_zeros=15, negative_zero=True),
+     {"slice_rows": 33}),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("rpw", [64, 16, 1])
+def test_plan_structure_and_roundtrip(name, make, kw, rpw):
+    A = make()
+    P = Plan(A, rows_per_wave=rpw, **kw)
+    st = _full_check(A, P)
+    s = P.stats()
+    assert s["nnz_ell"] == st["nnz_ell"] and s["nnz_er"] == st["nnz_er"]
+    assert s["rows_per_slice"] == rpw and s["lanes_per_row"] == 64 // rpw
+
+
+@pytest.mark.parametrize("cap", [1, 5, 9])
+def test_width_cap(cap):
+    A = matgen.stencil3d(12, perm_seed=1, val_seed=2)
+    P = Plan(A, slice_rows=600, ell_width_cap=cap)
+    _full_check(A, P, width_cap=cap)
+    assert P.arrays()["row_ell_len"].max() <= cap
+
+
+def test_integer_layout_exact():
+    A = matgen.poisson2d(40, perm_seed=11)
+    x = matgen.integer_vector(A.n_rows, 12)
+    P = Plan(A, slice_rows=300, rows_per_wave=8)
+    v = P.arrays()
+    perm = v["perm"]
+    assert np.array_equal(layout_spmv(v, x[perm]), oracle.spmv(A, x)[perm])
+
+
+def test_block_diagonal_has_no_residual():
+    """Connected blocks no larger than a partition: a good partitioner cuts no
+    edge, so the residual part is empty."""
+    A = matgen.block_diagonal([100] * 6, seed=5, density=0.1)
+    P = Plan(A, slice_rows=100, imbalance_pct=1)
+    st = _full_check(A, P)
+    assert st["nnz_er"] == 0
+
+
+def test_partitioner_beats_scrambled_blocks():
+    """Configuration 1 is randomly relabelled: consecutive blocks of the given
+    order cut almost everything, the graph partitioner very little."""
+    A = matgen.config_matrix(1)
+    nat = Plan(A, slice_rows=512, partitioner=1).stats()
+    ml = Plan(A, slice_rows=512).stats()
+    assert nat["nnz_er"] / nat["nnz"] > 0.5
+    assert ml["nnz_er"] / ml["nnz"] < 0.08
+
+
+def test_eq1_default_slice_rows():
+    A = matgen.stencil3d(100, points=7)   # n = 1e6
+    n = A.n_rows
+    K, vec = oracle.eq1_rule(n, 8, 256, 160 * 1024)
+    P = Plan(A, partitioner=1)
+    s = P.stats()
+    assert s["eq1_K"] == K and s["slice_rows"] == vec == 3907
+    assert s["nparts"] == -(-n // vec)
+    # small n: the floor at min(n, 512)
+    B = matgen.config_matrix(1)
+    assert Plan(B, partitioner=1).stats()["slice_rows"] == 512
+
+
+def test_partition_sizes_within_cap():
+    A = matgen.stencil3d(20, perm_seed=2, val_seed=3)
+    P = Plan(A, slice_rows=500, imbalance_pct=2)
+    ps = P.arrays()["part_start"]
+    assert np.diff(ps).max() <= 510
+    assert np.diff(ps).min() > 0
+
+
+def test_determinism_same_seed():
+    A = matgen.stencil3d(14, perm_seed=2, val_seed=3)
+    a = Plan(A, slice_rows=400, seed=5).arrays()
+    b = Plan(A, slice_rows=400, seed=5).arrays()
+    for k in ("perm", "part_start", "ell_val", "ell_col", "er_col", "slice_meta"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_tiny_and_empty():
+    for n in (0, 1, 2, 65):
+        A = matgen.random_small(n, 0.5, 3) if n else matgen.Csr(0, 0, np.zeros(1, np.int64),
+                                                                np.zeros(0, np.int32), np.zeros(0))
+        P = Plan(A)
+        if n:
+            _full_check(A, P)
+        assert P.stats()["n"] == n
+    A = matgen.random_small(50, 0.0, 1)     # no entries at all
+    P = Plan(A, slice_rows=16)
+    _full_check(A, P)
+    assert P.stats()["nnz"] == 0
+
+
+def test_fp32_plan_values_rounded():
+    A = matgen.stencil3d(10, perm_seed=1, val_seed=2)
+    P = Plan(A, slice_rows=300, value_dtype=1)
+    _full_check(A, P, value_dtype=np.float32, tau_x=4)
+
+
+@pytest.mark.parametrize("mutate,status", [
+    (lambda A: setattr(A, "n_cols", A.n_cols + 1), _abi.EHYB_EUNSUPPORTED),
+    (lambda A: A.col.__setitem__(slice(1, 3), A.col[1:3][::-1].copy()), _abi.EHYB_EINVAL),
+    (lambda A: A.col.__setitem__(1, A.col[0]), _abi.EHYB_EINVAL),
+    (lambda A: A.col.__setitem__(0, A.n_cols + 5), _abi.EHYB_EINVAL),
+    (lambda A: A.col.__setitem__(0, -1), _abi.EHYB_EINVAL),
+])
+def test_invalid_input_rejected(mutate, status):
+    A = matgen.poisson2d(6)
+    mutate(A)
+    with pytest.raises(EhybError) as e:
+        Plan(A)
+    assert e.value.status == status
+
+
+def test_row_ptr_inconsistent():
+    A = matgen.poisson2d(6)
+    A.row_ptr = A.row_ptr.copy()
+    A.row_ptr[3], A.row_ptr[4] = A.row_ptr[4], A.row_ptr[3]
+    with pytest.raises(EhybError) as e:
+        Plan(A)
+    assert e.value.status == _abi.EHYB_EINVAL
+
+
+@pytest.mark.parametrize("kw", [{"slice_rows": 20481}, {"rows_per_wave": 3}, {"rows_per_wave": 128},
+                                {"value_dtype": 7}, {"lds_bytes": 200000}, {"imbalance_pct": -1},
+                                {"partitioner": 5}, {"ell_width_cap": -2}])
+def test_invalid_params_rejected(kw):
+    A = matgen.poisson2d(8)
+    with pytest.raises(EhybError) as e:
+        Plan(A, **kw)
+    assert e.value.status == _abi.EHYB_EINVAL
+
+
+def test_spmv_before_upload_is_state_error():
+    A = matgen.poisson2d(8)
+    P = Plan(A)
+    lib = _abi.load()
+    dummy = ctypes.c_void_p(0x1000)
+    st = lib.ehyb_spmv(P.handle, dummy, ctypes.c_void_p(0x2000), 1, None)
+    assert st == _abi.EHYB_ESTATE
+    assert b"upload" in lib.ehyb_last_error()
+    assert lib.ehyb_spmv(P.handle, None, dummy, 1, None) == _abi.EHYB_EINVAL
+    assert lib.ehyb_spmv(P.handle, dummy, dummy, 7, None) == _abi.EHYB_EINVAL
+
+
+def test_save_load_roundtrip(tmp_path):
+    A = matgen.stencil3d(12, perm_seed=7, val_seed=8)
+    P = Plan(A, slice_rows=500, rows_per_wave=32)
+    path = str(tmp_path / "plan.ehyb")
+    P.save(path)
+    Q = Plan.load(path)
+    a, b = P.arrays(), Q.arrays()
+    for k in a:
+        if isinstance(a[k], np.ndarray):
+            assert np.array_equal(a[k], b[k]), k
+        else:
+            assert a[k] == b[k], k
+    _full_check(A, Q)
+    # corrupt one byte in the middle, and truncate
+    raw = bytearray(open(path, "rb").read())
+    raw[len(raw) // 2] ^= 0xFF
+    bad = str(tmp_path / "bad.ehyb")
+    open(bad, "wb").write(bytes(raw))
+    with pytest.raises(EhybError) as e:
+        Plan.load(bad)
+    assert e.value.status == _abi.EHYB_EINVAL
+    open(bad, "wb").write(open(path, "rb").read()[:100])
+    with pytest.raises(EhybError):
+        Plan.load(bad)
+    with pytest.raises(EhybError):
+        Plan.load(str(tmp_path / "missing.ehyb"))
+
+
+def test_algorithmic_bytes_formula():
+    A = matgen.stencil3d(12, perm_seed=1, val_seed=2)
+    P = Plan(A, slice_rows=400)
+    s = P.stats()
+    want = (s["ell_slots"] * 10 + s["er_slots"] * 12 + s["nslices"] * 16 + (s["nparts"] + 1) * 8
+            + 2 * s["n"] * 8)
+    assert s["algorithmic_bytes"] == want
+
+
+def test_host_threads_do_not_change_the_plan():
+    A = matgen.stencil3d(14, perm_seed=4, val_seed=5)
+    a = Plan(A, slice_rows=500, n_threads=1).arrays()
+    b = Plan(A, slice_rows=500, n_threads=4).arrays()
+    for k in ("perm", "ell_val", "ell_col", "er_val", "er_col", "slice_meta"):
+        assert np.array_equal(a[k], b[k]), k
+    assert os.environ.get("OMP_NUM_THREADS", "") == os.environ.get("OMP_NUM_THREADS", "")
