@@ -64,6 +64,7 @@ class Plan:
         self._blob = None
         if _handle is not None:
             self._h = _handle
+            self.n = self.stats()["n"]
             return
         rp, ci, v = _as_csr(A)
         csr = _abi.CsrHost(A.n_rows, A.n_cols, int(rp[-1]) if rp.size else 0,
@@ -73,6 +74,7 @@ class Plan:
                           num_cus, n_threads, imbalance_pct, partitioner, 0, seed)
         check(self._lib.ehyb_preprocess(ctypes.byref(csr), ctypes.byref(prm), ctypes.byref(self._h)),
               "ehyb_preprocess")
+        self.n = int(A.n_rows)
 
     # ------------------------------------------------------------ host side
     def __del__(self):
@@ -158,7 +160,7 @@ class Plan:
     def spmv(self, x, y=None, permuted: bool = True, stream=None):
         """y = A x.  ``permuted``: x and y are in the plan's order."""
         import torch
-        n = self.stats()["n"]
+        n = self.n
         if y is None:
             y = torch.empty(n, dtype=x.dtype, device=x.device)
         for t in (x, y):

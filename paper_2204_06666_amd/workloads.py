@@ -1,0 +1,26 @@
+"""Named workloads and the plan parameters the benchmark times them with.
+
+The headline workload is the randomly relabelled 27-point stencil on a 100^3
+grid (1,000,000 rows, 26,463,592 stored entries, FP64).  Its plan parameters
+live here so that the benchmark and the full-size parity test launch the same
+configuration.
+"""
+
+HEADLINE = {
+    "name": "stencil27-100^3",
+    "workload": "27-point stencil on a 100^3 grid, nodes randomly relabelled (seed 2000), "
+                "off-diagonals ~U[-1,1] (seed 2001), dominant diagonal; x ~U[-1,1] (seed 2002); "
+                "FP64 values, FP64 x/y/accumulation",
+    "config": 2,
+    "n": 1_000_000,
+    "nnz": 26_463_592,
+    "x_seed": 2002,
+}
+
+# Plan parameters of the headline run (zero = the Eq. 1-2 / library default).
+HEADLINE_PARAMS = {
+    "slice_rows": 0,
+    "rows_per_wave": 64,
+    "ell_width_cap": 0,
+    "seed": 0,
+}

@@ -1,0 +1,169 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance: per row |y_i - yhat_i| <= 1e-12 * sum_j |a_ij x_j| (exact where the
+sum is 0); integer-valued inputs must match bit for bit."""
+import numpy as np
+import pytest
+
+import matgen
+import oracle
+from paper_2204_06666_amd import EhybError, Plan, _abi, csr_spmv, probe_copy, probe_read
+from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+import torch as _torch  # noqa: E402  (imported at collection: the first import can be slow)
+
+
+@pytest.fixture(scope="module")
+def torch():
+    assert _torch.cuda.is_available(), "GPU tests need a GPU"
+    return _torch
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def _ehyb(torch, A, x, permuted=True, **kw):
+    P = Plan(A, **kw).upload("cuda:0")
+    perm = P.perm()
+    if permuted:
+        yp = P.spmv(_dev(torch, x[perm])).cpu().numpy()
+        y = np.empty_like(yp)
+        y[perm] = yp
+    else:
+        y = P.spmv(_dev(torch, x), permuted=False).cpu().numpy()
+    torch.cuda.synchronize()
+    return y, P
+
+
+def _check(A, x, y, what):
+    print(f"[parity] {what} n={A.n_rows} nnz={A.nnz}", flush=True)
+    return oracle.assert_close(y, oracle.spmv(A, x), oracle.abs_scale(A, x), TOL, what)
+
+
+@pytest.mark.parametrize("rpw", [64, 32, 16, 8, 4, 2, 1])
+@pytest.mark.parametrize("permuted", [True, False])
+def test_config1_parity(torch, rpw, permuted):
+    A = matgen.config_matrix(1)
+    x = matgen.uniform_vector(A.n_rows, matgen.CONFIG_SEEDS[1] + 2)
+    y, _ = _ehyb(torch, A, x, permuted, rows_per_wave=rpw)
+    _check(A, x, y, f"cfg1 rpw={rpw} permuted={permuted}")
+
+
+@pytest.mark.parametrize("rpw", [64, 8])
+def test_integer_poisson_bit_exact(torch, rpw):
+    A = matgen.config_matrix(1)
+    x = matgen.integer_vector(A.n_rows, 77)
+    y, _ = _ehyb(torch, A, x, rows_per_wave=rpw, slice_rows=300)
+    print(f"[parity] integer poisson rpw={rpw}", flush=True)
+    assert np.array_equal(y, oracle.spmv(A, x))
+
+
+CASES = [
+    ("stencil27-30", lambda: matgen.stencil3d(30, perm_seed=5, val_seed=6), {"slice_rows": 2000}),
+    ("stencil27-30-small-parts", lambda: matgen.stencil3d(30, perm_seed=5, val_seed=6), {"slice_rows": 130}),
+    ("knn", lambda: matgen.knn_fem(3000, perm_seed=1, pt_seed=2, val_seed=3), {"slice_rows": 1500}),
+    ("powerlaw", lambda: matgen.powerlaw(20000, exponent=2.2, mean_deg=10, seed=4), {"slice_rows": 2500}),
+    ("edge", lambda: matgen.random_small(300, 0.03, 9, empty_rows=30, dense_row=True,
+                                         explicit_zeros=20, negative_zero=True), {"slice_rows": 70}),
+    ("natural-order", lambda: matgen.stencil3d(24, points=7, val_seed=3), {"slice_rows": 1000, "partitioner": 1}),
+    ("width-cap", lambda: matgen.stencil3d(20, perm_seed=1, val_seed=2), {"slice_rows": 900, "ell_width_cap": 7}),
+    ("max-slice", lambda: matgen.stencil3d(30, perm_seed=8, val_seed=9), {"slice_rows": 19800, "imbalance_pct": 3}),
+]
+
+
+@pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("rpw", [64, 16, 4])
+def test_matrix_families(torch, name, make, kw, rpw):
+    A = make()
+    x = matgen.uniform_vector(A.n_rows, 123)
+    y, P = _ehyb(torch, A, x, rows_per_wave=rpw, **kw)
+    _check(A, x, y, f"{name} rpw={rpw} parts={P.stats()['nparts']}")
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 129])
+def test_tiny_ragged(torch, n):
+    A = matgen.random_small(n, 0.4, n + 3, empty_rows=min(2, n - 1))
+    x = matgen.uniform_vector(n, 5)
+    y, _ = _ehyb(torch, A, x, slice_rows=max(1, n // 2))
+    _check(A, x, y, f"tiny n={n}")
+
+
+def test_all_empty_rows_give_positive_zero(torch):
+    A = matgen.random_small(100, 0.0, 1)
+    x = matgen.uniform_vector(100, 2)
+    y, _ = _ehyb(torch, A, x, slice_rows=40)
+    assert np.all(y == 0) and not np.signbit(y).any()
+
+
+def test_bitwise_determinism(torch):
+    A = matgen.stencil3d(40, perm_seed=11, val_seed=12)
+    P = Plan(A, slice_rows=3000).upload("cuda:0")
+    x = _dev(torch, matgen.uniform_vector(A.n_rows, 13))
+    y0 = P.spmv(x).clone()
+    for _ in range(20):
+        y = P.spmv(x)
+        assert torch.equal(y.view(torch.int64), y0.view(torch.int64))
+    print("[parity] determinism ok", flush=True)
+
+
+def test_plan_file_gives_same_bits(torch, tmp_path):
+    A = matgen.stencil3d(16, perm_seed=3, val_seed=4)
+    P = Plan(A, slice_rows=1000).upload("cuda:0")
+    path = str(tmp_path / "p.ehyb")
+    P.save(path)
+    Q = Plan.load(path).upload("cuda:0")
+    x = _dev(torch, matgen.uniform_vector(A.n_rows, 3))
+    assert torch.equal(P.spmv(x), Q.spmv(x))
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 4, 8, 16, 32, 64])
+def test_csr_baseline_parity(torch, lanes):
+    A = matgen.stencil3d(30, perm_seed=5, val_seed=6)
+    x = matgen.uniform_vector(A.n_rows, 4)
+    rp = _dev(torch, A.row_ptr.astype(np.int32))
+    y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda:0")
+    csr_spmv(rp, _dev(torch, A.col), _dev(torch, A.val), _dev(torch, x), y, lanes)
+    _check(A, x, y.cpu().numpy(), f"csr lanes={lanes}")
+
+
+def test_headline_full_size(torch):
+    """The benchmarked workload at full size, in the benchmark's launch
+    configuration: every row against the oracle."""
+    A = matgen.config_matrix(HEADLINE["config"])
+    assert A.n_rows == HEADLINE["n"] and A.nnz == HEADLINE["nnz"]
+    x = matgen.uniform_vector(A.n_rows, HEADLINE["x_seed"])
+    y, P = _ehyb(torch, A, x, **HEADLINE_PARAMS)
+    w = _check(A, x, y, "headline")
+    print(f"[parity] headline worst scaled error {w:.2e} stats {P.stats()['nparts']} parts", flush=True)
+    y2, _ = _ehyb(torch, A, x, permuted=False, **HEADLINE_PARAMS)
+    _check(A, x, y2, "headline unpermuted")
+    # the comparator on the same input
+    rp = _dev(torch, A.row_ptr.astype(np.int32))
+    yc = torch.empty(A.n_rows, dtype=torch.float64, device="cuda:0")
+    csr_spmv(rp, _dev(torch, A.col), _dev(torch, A.val), _dev(torch, x), yc, 0)
+    _check(A, x, yc.cpu().numpy(), "headline csr")
+
+
+def test_errors_on_device(torch):
+    A = matgen.poisson2d(16)
+    P = Plan(A).upload("cuda:0")
+    x = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(EhybError) as e:
+        P.spmv(x, x)
+    assert e.value.status == _abi.EHYB_EINVAL
+    with pytest.raises(ValueError):
+        P.spmv(x.float())
+
+
+def test_probes(torch):
+    src = torch.arange(1 << 20, dtype=torch.int32, device="cuda:0")
+    dst = torch.zeros_like(src)
+    probe_copy(src, dst)
+    sink = torch.zeros(65536, dtype=torch.int64, device="cuda:0")
+    probe_read(src, sink)
+    torch.cuda.synchronize()
+    assert torch.equal(src, dst)
