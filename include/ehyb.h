@@ -82,14 +82,18 @@ typedef struct {
 typedef struct {
     int32_t slice_rows;     /* target rows per partition (x-slice length).
                                0 = Eq. 1-2: smallest K with n*tau/(K*P) < lds_bytes,
-                               VecSize = ceil(n/(K*P)), floored at min(n, 512). */
+                               VecSize = ceil(n/(K*P)), floored at min(n, 512).
+                               At most lds_bytes/tau and 65536 rows. */
     int32_t ell_width_cap;  /* max ELL entries per row; 0 = unlimited (the
                                paper's split by partition only) */
     int32_t rows_per_wave;  /* rows per 64-lane wavefront row-slice, a power of
                                two in [1, 64]; 64/rows_per_wave lanes share a
                                row. 0 = 64 (one lane per row) */
     int32_t value_dtype;    /* ehyb_dtype; 0 = EHYB_F64 */
-    int32_t lds_bytes;      /* x-slice budget per workgroup; 0 = 160 KiB */
+    int32_t lds_bytes;      /* LDS budget per workgroup; 0 = 160 KiB.  Each
+                               partition row holds its x element and a
+                               residual accumulator there (tau = 2 * bytes of
+                               an x element in Eq. 1) */
     int32_t num_cus;        /* P in Eq. 1; 0 = 256 */
     int32_t n_threads;      /* host threads; 0 = all available */
     int32_t imbalance_pct;  /* allowed overfill of a partition above
@@ -109,11 +113,12 @@ typedef struct {
     int64_t algorithmic_bytes;/* bytes one permuted-space SpMV must move, each
                                  array element once: ELL and residual slots
                                  (values + columns, padding included), slice
-                                 and partition metadata, x once, y once.  The
-                                 residual part's x gathers re-read x and are
-                                 not counted. */
-    int32_t nparts;           /* partitions (workgroup-sized x-slices) */
-    int32_t nslices;          /* row-slices (one wavefront task each) */
+                                 metadata and residual row indices, partition
+                                 bounds, x once, y once.  The residual part's
+                                 x gathers re-read x and are not counted. */
+    int32_t nparts;           /* partitions (one workgroup each) */
+    int32_t nslices;          /* ELL row-slices */
+    int32_t ner_slices;       /* residual row-slices */
     int32_t slice_rows;       /* target rows per partition actually used */
     int32_t max_part_rows;    /* largest partition */
     int32_t rows_per_slice;   /* C = rows_per_wave */
@@ -121,35 +126,52 @@ typedef struct {
     int32_t kc;               /* ELL entries per lane per load step */
     int32_t value_dtype;      /* ehyb_dtype */
     int32_t eq1_K;            /* K of Eq. 1 for this n (informational) */
-    int32_t reserved;
     double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */
 } ehyb_plan_stats;
 
 /* Read-only views of a plan's host arrays (owned by the plan, valid until
- * ehyb_plan_destroy).  Layout of the two parts, for row r (0 <= r < C) of
- * row-slice s and its k-th entry in ascending permuted column order:
+ * ehyb_plan_destroy).
+ *
+ * Rows: partition p owns permuted rows [part_start[p], part_start[p+1]);
+ * inside it rows are in non-increasing ELL count.
+ *
+ * ELL part: partition p's rows are cut into row-slices of C = 64/L rows,
+ * slices [slice_start[p], slice_start[p+1]); row r of ELL slice s is local
+ * row (s - slice_start[p])*C + r.  ell_meta[4s..4s+3] = slot offset, step
+ * count, and a 64-bit mask (low word, high word) whose bit r says that row r
+ * also has residual entries.  Columns are offsets into the partition's
+ * x-slice (local, 16-bit).
+ *
+ * Residual part: the rows of partition p with residual entries, sorted by
+ * non-increasing residual count (ties by local row), are cut into row-slices
+ * of C rows, slices [er_slice_start[p], er_slice_start[p+1]); er_row[e*C + r]
+ * is the local row of row r of residual slice e (0xFFFF past the last row).
+ * er_meta[2e..2e+1] = slot offset, step count.  Columns are permuted global
+ * indices.
+ *
+ * Slots: entry k (ascending permuted column) of row r of a slice with slot
+ * offset `off` lives at
  *   t = k / (L*KC), u = (k / KC) % L, c = k % KC, lane = r*L + u,
- *   slot = off[s] + (t*64 + lane)*KC + c,
- * with (off, steps) = slice_meta[4s+0], [4s+1] and KC = kc for the ELL part,
- * slice_meta[4s+2], [4s+3] and KC = 1 for the residual part.  Each step of a
- * row-slice holds 64*KC slots.  Row r of slice s is permuted row
- * part_start[p] + (s - slice_start[p])*C + r for the partition p holding s.
- * ELL columns are offsets from part_start[p]; residual columns are permuted
- * global indices.  Padding slots hold +0.0 and column 0. */
+ *   slot = off + (t*64 + lane)*KC + c,
+ * with KC = kc in the ELL part and KC = 1 in the residual part.  Each step of
+ * a slice holds 64*KC slots.  Padding slots hold +0.0 and column 0. */
 typedef struct {
     int64_t n;
-    int32_t nparts, nslices, lanes_per_row, kc, value_dtype, reserved;
+    int32_t nparts, nslices, ner_slices, lanes_per_row, kc, value_dtype;
     int64_t ell_slots, er_slots;
-    const int32_t *perm;        /* [n] new index -> original index */
-    const int32_t *part_start;  /* [nparts + 1] first permuted row of each partition */
-    const int32_t *slice_start; /* [nparts + 1] first row-slice of each partition */
-    const uint32_t *slice_meta; /* [4 * nslices] ell_off, ell_steps, er_off, er_steps */
-    const void *ell_val;        /* [ell_slots] values, value_dtype */
-    const uint16_t *ell_col;    /* [ell_slots] local columns */
-    const void *er_val;         /* [er_slots] values, value_dtype */
-    const int32_t *er_col;      /* [er_slots] permuted global columns */
-    const int32_t *row_ell_len; /* [n] ELL entries of each permuted row */
-    const int32_t *row_er_len;  /* [n] residual entries of each permuted row */
+    const int32_t *perm;           /* [n] new index -> original index */
+    const int32_t *part_start;     /* [nparts + 1] */
+    const int32_t *slice_start;    /* [nparts + 1] first ELL slice of each partition */
+    const int32_t *er_slice_start; /* [nparts + 1] first residual slice of each partition */
+    const uint32_t *ell_meta;      /* [4 * nslices] */
+    const uint32_t *er_meta;       /* [2 * ner_slices] */
+    const uint16_t *er_row;        /* [C * ner_slices] */
+    const void *ell_val;           /* [ell_slots] values, value_dtype */
+    const uint16_t *ell_col;       /* [ell_slots] local columns */
+    const void *er_val;            /* [er_slots] values, value_dtype */
+    const int32_t *er_col;         /* [er_slots] permuted global columns */
+    const int32_t *row_ell_len;    /* [n] ELL entries of each permuted row */
+    const int32_t *row_er_len;     /* [n] residual entries of each permuted row */
 } ehyb_plan_arrays;
 
 typedef struct ehyb_plan ehyb_plan;
@@ -195,6 +217,12 @@ EHYB_API ehyb_status ehyb_plan_upload(ehyb_plan *plan, void *dev_blob, size_t by
  * y is overwritten; the result is bitwise deterministic. */
 EHYB_API ehyb_status ehyb_spmv(const ehyb_plan *plan, const void *x, void *y, uint32_t flags,
                       void *stream);
+
+/* Launch shape of ehyb_spmv: wavefronts per workgroup (one workgroup per
+ * partition), one of 4, 8, 16; 0 = the library's choice.  Applies to later
+ * ehyb_spmv calls on this plan; does not change results (each row is summed by
+ * one fixed lane group in one fixed order whatever the shape). */
+EHYB_API ehyb_status ehyb_plan_set_launch(ehyb_plan *plan, int32_t waves_per_wg);
 
 /* x_perm[i] = x[perm[i]] and y[perm[i]] = y_perm[i] on the device (the
  * reordering applied to vectors; FP64 for FP64 plans). */

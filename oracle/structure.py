@@ -18,20 +18,24 @@ properties the paper fixes for the format:
 * the union of both parts is exactly P A P^T, values bit for bit (the reorder
   of Alg. 2 moves values without touching them).
 
-Layout rules being checked (row-slice = C = 64 / L consecutive permuted rows,
-one 64-lane wavefront per row-slice, L lanes per row, KC consecutive entries
-per lane per step):
+Layout rules being checked (row-slice = C = 64 / L rows, one 64-lane
+wavefront per row-slice, L lanes per row, KC consecutive entries per lane per
+step).  ELL part: partition p's rows, in order, cut into row-slices; row r of
+ELL slice s is local row (s - slice_start[p])*C + r.  Residual part: the rows
+of partition p that have residual entries, by non-increasing residual count
+(ties by local row), cut into row-slices; row r of residual slice e is local
+row er_row[e, r] (0xFFFF: none).  In either part
 
-    entry k of row r (0 <= r < C) of row-slice s lives at
+    entry k (ascending column) of row r of a slice with slot offset `off` lives at
         t = k // (L*KC), u = (k // KC) % L, c = k % KC, lane = r*L + u,
-        slot = off[s] + (t*64 + lane)*KC + c,
-    with (off, steps) = (ell_off, ell_steps) and KC = kc for the ELL part, and
-    (er_off, er_steps) with KC = 1 for the residual part.
+        slot = off + (t*64 + lane)*KC + c,
+    with KC = kc in the ELL part and KC = 1 in the residual part.
 
 ``view`` is a mapping with the keys: n, nparts, L, kc, perm, part_start,
-slice_start, slice_meta (uint32 [nslices, 4]: ell_off, ell_steps, er_off,
-er_steps), ell_val, ell_col (uint16), er_val, er_col (int32), row_ell_len,
-row_er_len.
+slice_start, er_slice_start, ell_meta (uint32 [nslices, 4]: offset, steps,
+residual-row mask low/high), er_meta (uint32 [ner_slices, 2]: offset, steps),
+er_row (uint16 [ner_slices, C]), ell_val, ell_col (uint16), er_val, er_col
+(int32), row_ell_len, row_er_len.
 """
 from __future__ import annotations
 
@@ -47,28 +51,46 @@ def _req(cond, msg):
         raise PlanError(msg)
 
 
+def _slice_rows(view, which: str):
+    """Per slice: (slot offset, steps, partition, rows[C]) with rows the
+    permuted row of each slice row or -1."""
+    L = int(view["L"])
+    C = 64 // L
+    part_start = np.asarray(view["part_start"], dtype=np.int64)
+    nparts = len(part_start) - 1
+    if which == "ell":
+        meta = np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)
+        starts = np.asarray(view["slice_start"], dtype=np.int64)
+    else:
+        meta = np.asarray(view["er_meta"], dtype=np.int64).reshape(-1, 2)
+        starts = np.asarray(view["er_slice_start"], dtype=np.int64)
+    ns = meta.shape[0]
+    _req(starts.shape == (nparts + 1,) and starts[0] == 0 and starts[-1] == ns,
+         f"{which} slice bounds do not cover its metadata")
+    _req((np.diff(starts) >= 0).all(), f"{which} slice bounds decrease")
+    part = np.repeat(np.arange(nparts), np.diff(starts))
+    if which == "ell":
+        local = (np.arange(ns) - starts[part])[:, None] * C + np.arange(C)[None, :]
+        size = (part_start[part + 1] - part_start[part])[:, None]
+        rows = np.where(local < size, part_start[part][:, None] + local, -1)
+    else:
+        er_row = np.asarray(view["er_row"], dtype=np.int64).reshape(ns, C)
+        rows = np.where(er_row != 0xFFFF, part_start[part][:, None] + er_row, -1)
+    return meta[:, 0], meta[:, 1], part, rows
+
+
 def _slots(view, which: str):
     """Enumerate every slot of one part.
 
-    Returns (slot, row, k, valid): the slot index, the permuted row it belongs
-    to (-1 for lanes past the partition end), the entry position within the
-    row, and whether it holds a real entry."""
+    Returns (slot, row, k, valid, part): the slot index, the permuted row it
+    belongs to (-1 for slice rows that hold no row), the entry position within
+    the row, whether it holds a real entry, and the slice's partition."""
     L = int(view["L"])
-    C = 64 // L
     kc = int(view["kc"]) if which == "ell" else 1
-    meta = np.asarray(view["slice_meta"], dtype=np.int64).reshape(-1, 4)
-    off = meta[:, 0] if which == "ell" else meta[:, 2]
-    steps = meta[:, 1] if which == "ell" else meta[:, 3]
+    off, steps, part_of_slice, rows = _slice_rows(view, which)
     rowlen = np.asarray(view["row_ell_len"] if which == "ell" else view["row_er_len"],
                         dtype=np.int64)
-    part_start = np.asarray(view["part_start"], dtype=np.int64)
-    slice_start = np.asarray(view["slice_start"], dtype=np.int64)
-    nslices = meta.shape[0]
-    # partition and first row of each slice
-    part_of_slice = np.repeat(np.arange(len(part_start) - 1), np.diff(slice_start))
-    _req(part_of_slice.size == nslices, "slice_start does not cover slice_meta")
-    row0 = part_start[part_of_slice] + (np.arange(nslices) - slice_start[part_of_slice]) * C
-    row_end = part_start[part_of_slice + 1]
+    nslices = off.shape[0]
     per = steps * 64 * kc
     total = int(per.sum())
     s_of = np.repeat(np.arange(nslices), per)
@@ -79,9 +101,8 @@ def _slots(view, which: str):
     r = lane // L
     u = lane % L
     k = (t * L + u) * kc + c
-    row = row0[s_of] + r
-    exists = row < row_end[s_of]
-    row = np.where(exists, row, -1)
+    row = rows[s_of, r] if total else np.zeros(0, dtype=np.int64)
+    exists = row >= 0
     valid = exists.copy()
     valid[exists] = k[exists] < rowlen[row[exists]]
     slot = off[s_of] + o
@@ -139,35 +160,56 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
     _req(L in (1, 2, 4, 8, 16, 32, 64), "lanes per row must divide 64")
     C = 64 // L
     slice_start = np.asarray(view["slice_start"], dtype=np.int64)
-    _req(np.array_equal(np.diff(slice_start), -(-sizes // C)), "slices per partition")
+    _req(np.array_equal(np.diff(slice_start), -(-sizes // C)), "ELL slices per partition")
 
-    meta = np.asarray(view["slice_meta"], dtype=np.int64).reshape(-1, 4)
     kc = int(view["kc"])
     ell_val = np.asarray(view["ell_val"])
     er_val = np.asarray(view["er_val"])
     ell_col = np.asarray(view["ell_col"])
     er_col = np.asarray(view["er_col"])
     _req(ell_col.dtype == np.uint16, "ELL columns must be 16-bit")
-    # slot ranges inside the arrays and disjoint
-    for off, steps, arr, width in ((meta[:, 0], meta[:, 1], ell_val, 64 * kc),
-                                   (meta[:, 2], meta[:, 3], er_val, 64)):
+    row_ell_len = np.asarray(view["row_ell_len"], dtype=np.int64)
+    row_er_len = np.asarray(view["row_er_len"], dtype=np.int64)
+    part_of_row = np.repeat(np.arange(nparts), sizes)
+
+    # residual rows: exactly the rows with residual entries, each once, in
+    # non-increasing residual count, ties by local row, padding at the end
+    er_row = np.asarray(view["er_row"], dtype=np.int64).reshape(-1, C)
+    er_start = np.asarray(view["er_slice_start"], dtype=np.int64)
+    for p in range(nparts):
+        rows_p = er_row[er_start[p]:er_start[p + 1]].reshape(-1)
+        real = rows_p[rows_p != 0xFFFF]
+        _req(np.array_equal(rows_p[:real.size], real), "residual padding rows before real rows")
+        want = np.nonzero(row_er_len[part_start[p]:part_start[p + 1]] > 0)[0]
+        _req(real.size == want.size and np.array_equal(np.sort(real), want),
+             "residual rows are not exactly the rows with residual entries")
+        _req(rows_p.size == -(-want.size // C) * C, "residual slices per partition")
+        cnt = row_er_len[part_start[p] + real]
+        _req((np.diff(cnt) <= 0).all(), "residual rows not in non-increasing residual count")
+        tie = np.diff(cnt) == 0
+        _req((np.diff(real)[tie] > 0).all(), "residual rows: unstable tie order")
+
+    for which, arr, width in (("ell", ell_val, 64 * kc), ("er", er_val, 64)):
+        off, steps, part_of_slice, rows = _slice_rows(view, which)
         end = off + steps * width
         _req((end <= arr.size).all(), "slot range past the end of its array")
         o = np.argsort(off, kind="stable")
         nz = steps[o] > 0
         _req((off[o][nz][1:] >= end[o][nz][:-1]).all(), "overlapping slot ranges")
-
-    row_ell_len = np.asarray(view["row_ell_len"], dtype=np.int64)
-    row_er_len = np.asarray(view["row_er_len"], dtype=np.int64)
-    part_of_row = np.repeat(np.arange(nparts), sizes)
-
-    # minimal widths: each slice's step count is what its longest row needs
-    for lens, steps, per in ((row_ell_len, meta[:, 1], L * kc), (row_er_len, meta[:, 3], L)):
-        if n:
-            need = np.zeros(meta.shape[0], dtype=np.int64)
-            slice_of_row = slice_start[part_of_row] + (np.arange(n) - part_start[part_of_row]) // C
-            np.maximum.at(need, slice_of_row, lens)
-            _req(np.array_equal(steps, -(-need // per)), "slice width is not its longest row")
+        # minimal widths: each slice's step count is what its longest row needs
+        lens = row_ell_len if which == "ell" else row_er_len
+        per = L * kc if which == "ell" else L
+        rl = np.where(rows >= 0, lens[np.maximum(rows, 0)], 0)
+        need = rl.max(axis=1) if rl.size else np.zeros(0, dtype=np.int64)
+        _req(np.array_equal(steps, -(-need // per)), f"{which} slice width is not its longest row")
+        if which == "ell":
+            meta = np.asarray(view["ell_meta"], dtype=np.uint64).reshape(-1, 4)
+            mask = meta[:, 2] | (meta[:, 3] << np.uint64(32))
+            has = np.where(rows >= 0, row_er_len[np.maximum(rows, 0)] > 0, False)
+            bits = (mask[:, None] >> np.arange(C, dtype=np.uint64)[None, :]) & np.uint64(1)
+            _req(np.array_equal(bits.astype(bool), has), "ELL residual-row mask is wrong")
+            if C < 64:
+                _req(((mask >> np.uint64(C)) == 0).all(), "ELL residual-row mask names a missing row")
 
     # padding slots
     for which, vals, cols in (("ell", ell_val, ell_col), ("er", er_val, er_col)):
@@ -183,6 +225,8 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
                  "ELL local column outside its partition")
         else:
             _req(((pc >= 0) & (pc < n)).all(), "residual padding column out of range")
+            _req((part_of_row[row[valid]] == part[valid]).all(),
+                 "residual row outside its slice's partition")
 
     row, col, val, in_ell = layout_entries(view)
     _req(((col >= 0) & (col < n)).all(), "column out of range")
@@ -221,6 +265,7 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
     nnz_er = int((~in_ell).sum())
     return {
         "nnz": int(B.nnz), "nnz_ell": int(in_ell.sum()), "nnz_er": nnz_er,
-        "ell_slots": int((meta[:, 1] * 64 * kc).sum()), "er_slots": int((meta[:, 3] * 64).sum()),
+        "ell_slots": int(np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)[:, 1].sum() * 64 * kc),
+        "er_slots": int(np.asarray(view["er_meta"], dtype=np.int64).reshape(-1, 2)[:, 1].sum() * 64),
         "er_fraction": nnz_er / max(1, B.nnz), "nparts": nparts,
     }

@@ -105,11 +105,16 @@ class Plan:
             buf = (ctypes.c_char * (count * np.dtype(dtype).itemsize)).from_address(addr)
             return np.frombuffer(buf, dtype=dtype).copy()
 
+        C = 64 // ar.lanes_per_row
+        nes = ar.ner_slices
         return dict(
             n=n, nparts=nparts, L=ar.lanes_per_row, kc=ar.kc, value_dtype=ar.value_dtype,
             perm=grab(ar.perm, n, np.int32), part_start=grab(ar.part_start, nparts + 1, np.int32),
             slice_start=grab(ar.slice_start, nparts + 1, np.int32),
-            slice_meta=grab(ar.slice_meta, 4 * ns, np.uint32).reshape(ns, 4),
+            er_slice_start=grab(ar.er_slice_start, nparts + 1, np.int32),
+            ell_meta=grab(ar.ell_meta, 4 * ns, np.uint32).reshape(ns, 4),
+            er_meta=grab(ar.er_meta, 2 * nes, np.uint32).reshape(nes, 2),
+            er_row=grab(ar.er_row, C * nes, np.uint16).reshape(nes, C),
             ell_val=grab(ar.ell_val, ar.ell_slots, vt), ell_col=grab(ar.ell_col, ar.ell_slots, np.uint16),
             er_val=grab(ar.er_val, ar.er_slots, vt), er_col=grab(ar.er_col, ar.er_slots, np.int32),
             row_ell_len=grab(ar.row_ell_len, n, np.int32), row_er_len=grab(ar.row_er_len, n, np.int32))
@@ -141,6 +146,11 @@ class Plan:
         b = ctypes.c_size_t()
         check(self._lib.ehyb_plan_device_bytes(self._h, ctypes.byref(b)), "device_bytes")
         return b.value
+
+    def set_launch(self, waves_per_wg: int = 0):
+        """Wavefronts per workgroup of spmv (0 = library choice); results are unchanged."""
+        check(self._lib.ehyb_plan_set_launch(self._h, waves_per_wg), "set_launch")
+        return self
 
     # ---------------------------------------------------------- device side
     def upload(self, device="cuda:0", stream=None):

@@ -33,18 +33,19 @@ class PlanStats(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nnz", c_i64), ("nnz_ell", c_i64), ("nnz_er", c_i64),
                 ("ell_slots", c_i64), ("er_slots", c_i64), ("n_er_rows", c_i64),
                 ("device_bytes", c_i64), ("algorithmic_bytes", c_i64),
-                ("nparts", c_i32), ("nslices", c_i32), ("slice_rows", c_i32),
+                ("nparts", c_i32), ("nslices", c_i32), ("ner_slices", c_i32), ("slice_rows", c_i32),
                 ("max_part_rows", c_i32), ("rows_per_slice", c_i32), ("lanes_per_row", c_i32),
-                ("kc", c_i32), ("value_dtype", c_i32), ("eq1_K", c_i32), ("reserved", c_i32),
+                ("kc", c_i32), ("value_dtype", c_i32), ("eq1_K", c_i32),
                 ("t_graph_s", ctypes.c_double), ("t_partition_s", ctypes.c_double),
                 ("t_reorder_s", ctypes.c_double), ("t_encode_s", ctypes.c_double)]
 
 
 class PlanArrays(ctypes.Structure):
-    _fields_ = [("n", c_i64), ("nparts", c_i32), ("nslices", c_i32), ("lanes_per_row", c_i32),
-                ("kc", c_i32), ("value_dtype", c_i32), ("reserved", c_i32),
+    _fields_ = [("n", c_i64), ("nparts", c_i32), ("nslices", c_i32), ("ner_slices", c_i32),
+                ("lanes_per_row", c_i32), ("kc", c_i32), ("value_dtype", c_i32),
                 ("ell_slots", c_i64), ("er_slots", c_i64),
-                ("perm", c_vp), ("part_start", c_vp), ("slice_start", c_vp), ("slice_meta", c_vp),
+                ("perm", c_vp), ("part_start", c_vp), ("slice_start", c_vp), ("er_slice_start", c_vp),
+                ("ell_meta", c_vp), ("er_meta", c_vp), ("er_row", c_vp),
                 ("ell_val", c_vp), ("ell_col", c_vp), ("er_val", c_vp), ("er_col", c_vp),
                 ("row_ell_len", c_vp), ("row_er_len", c_vp)]
 
@@ -64,6 +65,7 @@ SIGNATURES = {
     "ehyb_plan_device_bytes": (c_i32, [c_vp, ctypes.POINTER(c_size)]),
     "ehyb_plan_upload": (c_i32, [c_vp, c_vp, c_size, c_vp]),
     "ehyb_spmv": (c_i32, [c_vp, c_vp, c_vp, c_u32, c_vp]),
+    "ehyb_plan_set_launch": (c_i32, [c_vp, c_i32]),
     "ehyb_permute_x": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "ehyb_unpermute_y": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "ehyb_plan_save": (c_i32, [c_vp, ctypes.c_char_p]),

@@ -24,92 +24,164 @@ __device__ __forceinline__ int xcd_logical_id(int b, int nblocks) {
 }
 
 struct SpmvF64Args {
-    const int32_t* part_start;
-    const int32_t* slice_start;
-    const uint4* slice_meta;   // ell_off, ell_steps, er_off, er_steps
+    const int32_t* part_start;      // [nparts+1] first permuted row of each partition
+    const int32_t* slice_start;     // [nparts+1] first ELL row-slice of each partition
+    const int32_t* er_slice_start;  // [nparts+1] first residual row-slice of each partition
+    const uint4* ell_meta;          // slot offset, steps, residual-row mask (lo, hi)
+    const uint2* er_meta;           // slot offset, steps
+    const uint16_t* er_row;         // local row of each residual slice row, 0xFFFF = none
     const double* ell_val;
     const uint16_t* ell_col;
     const double* er_val;
     const int32_t* er_col;
-    const double* x;           // permuted order
-    double* y;                 // permuted order
-    int32_t nparts;
-    int32_t wgs_per_part;      // workgroups sharing one partition
+    const double* x;                // permuted order
+    double* y;                      // permuted order
+    int32_t lds_rows;               // rows reserved in each LDS array
 };
 
-// One workgroup stages its partition's x-slice in LDS (Alg. 3: the cached
-// vector), then each wavefront sweeps row-slices of that partition: 64 lanes,
-// L lanes per row, two ELL entries per lane per step (a 16-byte value load and
-// a 4-byte load of two 16-bit columns), multiply-add against the LDS copy,
-// then the row's residual entries against x in device memory, a reduction
-// over the L lanes of a row, and one store per row.  Row-slices are dealt to
-// wavefronts statically; the ELL and residual parts of a row are summed by the
-// same lane group, so y needs no atomics and the result is deterministic.
+constexpr int kEllChunk = 16;   // ELL steps whose loads are issued before any is used
+constexpr int kErChunk = 8;     // residual steps likewise
+constexpr int kStageRegs = 4;   // 16-byte x-slice loads per thread kept in flight
+
 template <int L>
-__global__ void __launch_bounds__(512) ehyb_spmv_f64_kernel(SpmvF64Args a) {
-    extern __shared__ double xs[];
+__device__ __forceinline__ double reduce_lanes(double v) {
+    if constexpr (L > 1) {
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    }
+    return v;
+}
+
+// One workgroup per partition (Alg. 3).  Phases:
+//  1. issue the loads of the partition's x-slice (held in registers);
+//  2. residual part: wavefronts take the partition's residual row-slices in
+//     turn, gather x from device memory and leave each row's sum in an LDS
+//     accumulator (each residual row is owned by one lane group, so a plain
+//     store suffices);
+//  3. write the x-slice to LDS; barrier;
+//  4. ELL part: wavefronts take row-slices from a workgroup counter (the
+//     balancing of Alg. 3), issue every load of a slice (up to kEllChunk steps
+//     of a 16-byte value pair and a 4-byte column pair per lane) before
+//     consuming any, multiply-add against the LDS x-slice, add the residual
+//     sum of rows that have one, and store y once.
+// The sum of a row is (ELL entries in column order) + (residual entries in
+// column order), fixed by the plan: results are bitwise reproducible.
+template <int L>
+__global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
+    extern __shared__ double lds[];
+    __shared__ int ell_next;
+    double* xs = lds;
+    double* yer = lds + a.lds_rows;
     constexpr int C = kWave / L;
-    const int logical = xcd_logical_id(blockIdx.x, gridDim.x);
-    const int p = logical / a.wgs_per_part;
-    const int sub = logical - p * a.wgs_per_part;
+    const int p = xcd_logical_id(blockIdx.x, gridDim.x);
     const int ps = a.part_start[p];
     const int sz = a.part_start[p + 1] - ps;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int lane = tid & (kWave - 1);
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nwaves = nthr >> 6;
+    const int r = lane / L;
+    if (tid == 0) ell_next = 0;
 
-    // stage the x-slice: 16-byte loads over the aligned body, scalar edges
-    {
-        const double* src = a.x + ps;
-        const int head = (int)(((uintptr_t)src >> 3) & 1);  // 1 if src is 8- but not 16-byte aligned
-        const int h = head < sz ? head : sz;
-        const int nvec = (sz - h) >> 1;
-        const double2* src2 = reinterpret_cast<const double2*>(src + h);
-        for (int i = threadIdx.x; i < nvec; i += blockDim.x) {
-            const double2 v = src2[i];
-            xs[h + 2 * i] = v.x;
-            xs[h + 2 * i + 1] = v.y;
-        }
-        if (threadIdx.x < h) xs[0] = src[0];
-        const int tail = h + 2 * nvec;
-        if ((int)threadIdx.x < sz - tail) xs[tail + threadIdx.x] = src[tail + threadIdx.x];
+    // 1. x-slice loads: 16-byte loads over the aligned body
+    const double* src = a.x + ps;
+    const int head = (int)(((uintptr_t)src >> 3) & 1);  // 1 if src is 8- but not 16-byte aligned
+    const int h = head < sz ? head : sz;
+    const int nvec = (sz - h) >> 1;
+    const double2* src2 = reinterpret_cast<const double2*>(src + h);
+    double2 stg[kStageRegs];
+#pragma unroll
+    for (int j = 0; j < kStageRegs; ++j) {
+        const int i = tid + j * nthr;
+        if (i < nvec) stg[j] = src2[i];
     }
+
+    // 2. residual part
+    const int e0 = a.er_slice_start[p], e1 = a.er_slice_start[p + 1];
+    for (int e = e0 + wave; e < e1; e += nwaves) {
+        const uint2 m = a.er_meta[e];
+        const double* ev = a.er_val + m.x + lane;
+        const int32_t* ec = a.er_col + m.x + lane;
+        double acc = 0.0;
+        for (uint32_t t0 = 0; t0 < m.y; t0 += kErChunk) {
+            int32_t c[kErChunk];
+            double v[kErChunk], xg[kErChunk];
+#pragma unroll
+            for (int j = 0; j < kErChunk; ++j)
+                if (t0 + j < m.y) {
+                    c[j] = ec[(size_t)(t0 + j) * kWave];
+                    v[j] = ev[(size_t)(t0 + j) * kWave];
+                }
+#pragma unroll
+            for (int j = 0; j < kErChunk; ++j)
+                if (t0 + j < m.y) xg[j] = a.x[c[j]];
+#pragma unroll
+            for (int j = 0; j < kErChunk; ++j)
+                if (t0 + j < m.y) acc = fma(v[j], xg[j], acc);
+        }
+        acc = reduce_lanes<L>(acc);
+        const uint16_t lr = a.er_row[(size_t)e * C + r];
+        if ((lane & (L - 1)) == 0 && lr != 0xFFFF) yer[lr] = acc;
+    }
+
+    // 3. x-slice into LDS
+#pragma unroll
+    for (int j = 0; j < kStageRegs; ++j) {
+        const int i = tid + j * nthr;
+        if (i < nvec) {
+            xs[h + 2 * i] = stg[j].x;
+            xs[h + 2 * i + 1] = stg[j].y;
+        }
+    }
+    for (int i = tid + kStageRegs * nthr; i < nvec; i += nthr) {
+        const double2 v = src2[i];
+        xs[h + 2 * i] = v.x;
+        xs[h + 2 * i + 1] = v.y;
+    }
+    if (tid < h) xs[0] = src[0];
+    const int tail = h + 2 * nvec;
+    if (tid < sz - tail) xs[tail + tid] = src[tail + tid];
     __syncthreads();
 
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nwaves = blockDim.x >> 6;
-    const int s0 = a.slice_start[p], s1 = a.slice_start[p + 1];
-    const int stride = a.wgs_per_part * nwaves;
-    const int r = lane / L;
-    for (int s = s0 + sub * nwaves + wave; s < s1; s += stride) {
-        const uint4 m = a.slice_meta[s];
-        double acc = 0.0;
+    // 4. ELL part
+    const int s0 = a.slice_start[p];
+    const int ns = a.slice_start[p + 1] - s0;
+    int item = wave;
+    uint4 m = item < ns ? a.ell_meta[s0 + item] : make_uint4(0, 0, 0, 0);
+    while (item < ns) {
+        int nxt = 0;
+        if (lane == 0) nxt = atomicAdd(&ell_next, 1);
+        nxt = __builtin_amdgcn_readfirstlane(nxt) + nwaves;
+        // the next slice's metadata travels while this slice streams
+        const uint4 mn = nxt < ns ? a.ell_meta[s0 + nxt] : make_uint4(0, 0, 0, 0);
         const double2* v2 = reinterpret_cast<const double2*>(a.ell_val + m.x) + lane;
         const uint32_t* c2 = reinterpret_cast<const uint32_t*>(a.ell_col + m.x) + lane;
-        uint32_t t = 0;
-        for (; t + 2 <= m.y; t += 2) {
-            const double2 va = v2[(size_t)t * kWave];
-            const uint32_t ca = c2[(size_t)t * kWave];
-            const double2 vb = v2[(size_t)(t + 1) * kWave];
-            const uint32_t cb = c2[(size_t)(t + 1) * kWave];
-            acc = fma(va.x, xs[ca & 0xFFFFu], acc);
-            acc = fma(va.y, xs[ca >> 16], acc);
-            acc = fma(vb.x, xs[cb & 0xFFFFu], acc);
-            acc = fma(vb.y, xs[cb >> 16], acc);
-        }
-        if (t < m.y) {
-            const double2 va = v2[(size_t)t * kWave];
-            const uint32_t ca = c2[(size_t)t * kWave];
-            acc = fma(va.x, xs[ca & 0xFFFFu], acc);
-            acc = fma(va.y, xs[ca >> 16], acc);
-        }
-        const double* ev = a.er_val + m.z + lane;
-        const int32_t* ec = a.er_col + m.z + lane;
-        for (uint32_t k = 0; k < m.w; ++k) acc = fma(ev[(size_t)k * kWave], a.x[ec[(size_t)k * kWave]], acc);
-        if constexpr (L > 1) {
+        double acc = 0.0;
+        for (uint32_t t0 = 0; t0 < m.y; t0 += kEllChunk) {
+            double2 v[kEllChunk];
+            uint32_t c[kEllChunk];
 #pragma unroll
-            for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+            for (int j = 0; j < kEllChunk; ++j)
+                if (t0 + j < m.y) {
+                    v[j] = v2[(size_t)(t0 + j) * kWave];
+                    c[j] = c2[(size_t)(t0 + j) * kWave];
+                }
+#pragma unroll
+            for (int j = 0; j < kEllChunk; ++j)
+                if (t0 + j < m.y) {
+                    acc = fma(v[j].x, xs[c[j] & 0xFFFFu], acc);
+                    acc = fma(v[j].y, xs[c[j] >> 16], acc);
+                }
         }
-        const int row = ps + (s - s0) * C + r;
-        if ((lane & (L - 1)) == 0 && row < ps + sz) a.y[row] = acc;
+        acc = reduce_lanes<L>(acc);
+        const int lr = item * C + r;
+        const uint64_t mask = ((uint64_t)m.w << 32) | m.z;
+        if ((lane & (L - 1)) == 0 && lr < sz) {
+            if ((mask >> r) & 1u) acc += yer[lr];
+            a.y[ps + lr] = acc;
+        }
+        item = nxt;
+        m = mn;
     }
 }
 
@@ -186,24 +258,14 @@ ehyb_status launch_status(const char* what) {
     return EHYB_OK;
 }
 
-struct LaunchShape {
-    int waves_per_wg;
-    int wgs_per_part;
-};
-
-// Waves per workgroup and workgroups per partition: enough wavefronts to keep
-// every CU busy (about 16 per CU), never more wavefronts on a partition than
-// it has row-slices.
-LaunchShape launch_shape(const ehyb_plan& P) {
-    LaunchShape sh{8, 1};
-    if (P.nparts == 0) return sh;
-    const int64_t per_part = (P.nslices + P.nparts - 1) / P.nparts;
-    sh.waves_per_wg = (int)std::max<int64_t>(1, std::min<int64_t>(8, per_part));
-    const int64_t target_waves = 256LL * 16;
-    int64_t w = (target_waves + (int64_t)P.nparts * sh.waves_per_wg - 1) / ((int64_t)P.nparts * sh.waves_per_wg);
-    const int64_t max_w = std::max<int64_t>(1, per_part / sh.waves_per_wg);
-    sh.wgs_per_part = (int)std::max<int64_t>(1, std::min<int64_t>(w, max_w));
-    return sh;
+// Wavefronts per workgroup: 16 (1024 threads) unless the plan sets another
+// shape; never more wavefronts than the largest partition has ELL row-slices.
+int launch_waves(const ehyb_plan& P) {
+    if (P.launch_waves > 0) return P.launch_waves;
+    const int64_t max_slices = (P.max_part_rows + P.C - 1) / P.C;
+    if (max_slices <= 4) return 4;
+    if (max_slices <= 8) return 8;
+    return 16;
 }
 
 template <int L>
@@ -212,7 +274,7 @@ void launch_spmv_f64(const SpmvF64Args& a, int nblocks, int threads, size_t lds,
     if (!lds_raised && lds > 64 * 1024) {
         // allow the full 160 KiB of gfx950 LDS as dynamic shared memory
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(&ehyb_spmv_f64_kernel<L>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024) != hipSuccess)
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64) != hipSuccess)
             (void)hipGetLastError();
         lds_raised = true;
     }
@@ -239,7 +301,10 @@ ehyb_status ehyb_plan_upload(ehyb_plan* P, void* dev_blob, size_t bytes, void* s
     } pieces[] = {
         {L.part_start, P->part_start.data(), P->part_start.size() * 4},
         {L.slice_start, P->slice_start.data(), P->slice_start.size() * 4},
-        {L.slice_meta, P->slice_meta.data(), P->slice_meta.size() * 4},
+        {L.er_slice_start, P->er_slice_start.data(), P->er_slice_start.size() * 4},
+        {L.ell_meta, P->ell_meta.data(), P->ell_meta.size() * 4},
+        {L.er_meta, P->er_meta.data(), P->er_meta.size() * 4},
+        {L.er_row, P->er_row.data(), P->er_row.size() * 2},
         {L.ell_val, P->ell_val.data(), P->ell_val.size()},
         {L.ell_col, P->ell_col.data(), P->ell_col.size() * 2},
         {L.er_val, P->er_val.data(), P->er_val.size()},
@@ -256,6 +321,14 @@ ehyb_status ehyb_plan_upload(ehyb_plan* P, void* dev_blob, size_t bytes, void* s
     P->dev_blob = dev_blob;
     P->dev_bytes = bytes;
     P->layout = L;
+    return EHYB_OK;
+}
+
+ehyb_status ehyb_plan_set_launch(ehyb_plan* P, int32_t waves_per_wg) {
+    if (!P) return fail(EHYB_EINVAL, "null argument");
+    if (waves_per_wg != 0 && waves_per_wg != 4 && waves_per_wg != 8 && waves_per_wg != 16)
+        return fail(EHYB_EINVAL, "waves_per_wg must be 0, 4, 8 or 16");
+    P->launch_waves = waves_per_wg;
     return EHYB_OK;
 }
 
@@ -314,29 +387,29 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     SpmvF64Args a;
     a.part_start = (const int32_t*)(blob + Ly.part_start);
     a.slice_start = (const int32_t*)(blob + Ly.slice_start);
-    a.slice_meta = (const uint4*)(blob + Ly.slice_meta);
+    a.er_slice_start = (const int32_t*)(blob + Ly.er_slice_start);
+    a.ell_meta = (const uint4*)(blob + Ly.ell_meta);
+    a.er_meta = (const uint2*)(blob + Ly.er_meta);
+    a.er_row = (const uint16_t*)(blob + Ly.er_row);
     a.ell_val = (const double*)(blob + Ly.ell_val);
     a.ell_col = (const uint16_t*)(blob + Ly.ell_col);
     a.er_val = (const double*)(blob + Ly.er_val);
     a.er_col = (const int32_t*)(blob + Ly.er_col);
     a.x = xin;
     a.y = yout;
-    a.nparts = P->nparts;
-    const LaunchShape sh = launch_shape(*P);
-    a.wgs_per_part = sh.wgs_per_part;
-    const int64_t nblocks = (int64_t)P->nparts * sh.wgs_per_part;
-    if (nblocks > INT32_MAX) return fail(EHYB_EUNSUPPORTED, "too many workgroups");
-    const size_t lds = (size_t)P->max_part_rows * 8;
-    if (lds > 160 * 1024) return fail(EHYB_EUNSUPPORTED, "x-slice larger than LDS");
-    const int threads = sh.waves_per_wg * kWave;
+    a.lds_rows = P->max_part_rows;
+    const int nblocks = P->nparts;
+    const size_t lds = (size_t)P->max_part_rows * 16;
+    if (lds > 160 * 1024 - 64) return fail(EHYB_EUNSUPPORTED, "partition larger than the LDS budget");
+    const int threads = launch_waves(*P) * kWave;
     switch (P->L) {
-        case 1: launch_spmv_f64<1>(a, (int)nblocks, threads, lds, s); break;
-        case 2: launch_spmv_f64<2>(a, (int)nblocks, threads, lds, s); break;
-        case 4: launch_spmv_f64<4>(a, (int)nblocks, threads, lds, s); break;
-        case 8: launch_spmv_f64<8>(a, (int)nblocks, threads, lds, s); break;
-        case 16: launch_spmv_f64<16>(a, (int)nblocks, threads, lds, s); break;
-        case 32: launch_spmv_f64<32>(a, (int)nblocks, threads, lds, s); break;
-        case 64: launch_spmv_f64<64>(a, (int)nblocks, threads, lds, s); break;
+        case 1: launch_spmv_f64<1>(a, nblocks, threads, lds, s); break;
+        case 2: launch_spmv_f64<2>(a, nblocks, threads, lds, s); break;
+        case 4: launch_spmv_f64<4>(a, nblocks, threads, lds, s); break;
+        case 8: launch_spmv_f64<8>(a, nblocks, threads, lds, s); break;
+        case 16: launch_spmv_f64<16>(a, nblocks, threads, lds, s); break;
+        case 32: launch_spmv_f64<32>(a, nblocks, threads, lds, s); break;
+        case 64: launch_spmv_f64<64>(a, nblocks, threads, lds, s); break;
         default: return fail(EHYB_EINVAL, "bad lanes per row");
     }
     ehyb_status st = launch_status("ehyb_spmv");

@@ -212,8 +212,9 @@ int64_t algorithmic_bytes(const ehyb_plan& p) {
     int64_t b = 0;
     b += p.ell_slots * (p.vbytes + 2);                 // ELL values + 16-bit columns
     b += p.er_slots * (p.vbytes + 4);                  // residual values + 32-bit columns
-    b += (int64_t)p.nslices * 16;                      // row-slice metadata
-    b += (int64_t)(p.nparts + 1) * 8;                  // partition + slice boundaries
+    b += (int64_t)p.nslices * 16;                      // ELL slice metadata
+    b += (int64_t)p.ner_slices * (8 + 2 * p.C);        // residual slice metadata + row indices
+    b += (int64_t)(p.nparts + 1) * 12;                 // partition and slice bounds
     b += p.n * p.xbytes;                               // x, each element once (slice staging)
     b += p.n * p.xbytes;                               // y, written once
     return b;
@@ -229,7 +230,10 @@ BlobLayout compute_layout(const ehyb_plan& p) {
     };
     L.part_start = take((size_t)(p.nparts + 1) * 4);
     L.slice_start = take((size_t)(p.nparts + 1) * 4);
-    L.slice_meta = take((size_t)p.nslices * 16);
+    L.er_slice_start = take((size_t)(p.nparts + 1) * 4);
+    L.ell_meta = take((size_t)p.nslices * 16);
+    L.er_meta = take((size_t)p.ner_slices * 8);
+    L.er_row = take((size_t)p.ner_slices * p.C * 2);
     L.ell_val = take((size_t)p.ell_slots * p.vbytes);
     L.ell_col = take((size_t)p.ell_slots * 2);
     L.er_val = take((size_t)p.er_slots * p.vbytes);
@@ -241,11 +245,32 @@ BlobLayout compute_layout(const ehyb_plan& p) {
     return L;
 }
 
+// Residual position of every permuted row (e*C + r, or -1), from er_row.
+void build_er_pos(ehyb_plan& P) {
+    P.er_pos.assign((size_t)P.n, -1);
+    for (int32_t p = 0; p < P.nparts; ++p)
+        for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e)
+            for (int32_t r = 0; r < P.C; ++r) {
+                const uint16_t lr = P.er_row[(size_t)e * P.C + r];
+                if (lr != 0xFFFF) P.er_pos[P.part_start[p] + lr] = e * P.C + r;
+            }
+}
+
 }  // namespace ehyb
 
 using namespace ehyb;
 
 namespace {
+
+inline int64_t ell_slot_of(int64_t off, int32_t k, int32_t r, int L, int kc) {
+    const int64_t t = k / (L * kc), u = (k / kc) % L, c = k % kc;
+    return off + (t * kWave + (int64_t)r * L + u) * kc + c;
+}
+
+inline int64_t er_slot_of(int64_t off, int32_t k, int32_t r, int L) {
+    const int64_t t = k / L, u = k % L;
+    return off + t * kWave + (int64_t)r * L + u;
+}
 
 // Alg. 1 (classification and reordering) and Alg. 2 (moving entries into the
 // ELL and residual parts), given the partition vector.
@@ -292,47 +317,93 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
         P->row_ell_len[i] = ell_cnt[P->perm[i]];
         P->row_er_len[i] = er_cnt[P->perm[i]];
     }
+    // residual rows of each partition by non-increasing residual count (the
+    // extra-rows arrangement of Alg. 1), ties by local row
+    P->er_slice_start.assign(nparts + 1, 0);
+    std::vector<std::vector<uint16_t>> er_rows(nparts);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t p = 0; p < nparts; ++p) {
+        auto& v = er_rows[p];
+        const int32_t ps = P->part_start[p];
+        for (int32_t i = ps; i < P->part_start[p + 1]; ++i)
+            if (P->row_er_len[i] > 0) v.push_back((uint16_t)(i - ps));
+        std::stable_sort(v.begin(), v.end(), [&](uint16_t a, uint16_t b) {
+            return P->row_er_len[ps + a] > P->row_er_len[ps + b];
+        });
+    }
+    for (int32_t p = 0; p < nparts; ++p)
+        P->er_slice_start[p + 1] = P->er_slice_start[p] + (int32_t)((er_rows[p].size() + C - 1) / C);
+    P->nparts = nparts;
+    P->ner_slices = P->er_slice_start[nparts];
+    P->er_row.assign((size_t)P->ner_slices * C, 0xFFFF);
+    for (int32_t p = 0; p < nparts; ++p)
+        for (size_t j = 0; j < er_rows[p].size(); ++j)
+            P->er_row[(size_t)P->er_slice_start[p] * C + j] = er_rows[p][j];
+    build_er_pos(*P);
     P->t_reorder = now_s() - t0;
     t0 = now_s();
 
-    // row-slices: C consecutive rows of one partition; widths and offsets
+    // ELL row-slices: C consecutive rows of one partition
     P->slice_start.assign(nparts + 1, 0);
     for (int32_t p = 0; p < nparts; ++p)
         P->slice_start[p + 1] = P->slice_start[p] + (P->part_start[p + 1] - P->part_start[p] + C - 1) / C;
     const int32_t ns = P->slice_start[nparts];
     P->nslices = ns;
-    P->nparts = nparts;
     std::vector<int32_t> slice_part(ns);
     for (int32_t p = 0; p < nparts; ++p)
         for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) slice_part[s] = p;
-    std::vector<int64_t> ell_steps(ns), er_steps(ns);
+    std::vector<int64_t> ell_steps(ns);
+    std::vector<uint64_t> er_mask(ns, 0);
 #pragma omp parallel for schedule(static)
     for (int32_t s = 0; s < ns; ++s) {
         const int32_t p = slice_part[s];
         const int32_t r0 = P->part_start[p] + (s - P->slice_start[p]) * C;
         const int32_t r1 = std::min(r0 + C, P->part_start[p + 1]);
-        int32_t me = 0, mr = 0;
+        int32_t me = 0;
+        uint64_t mask = 0;
         for (int32_t r = r0; r < r1; ++r) {
             me = std::max(me, P->row_ell_len[r]);
-            mr = std::max(mr, P->row_er_len[r]);
+            if (P->row_er_len[r] > 0) mask |= 1ull << (r - r0);
         }
         ell_steps[s] = (me + L * kc - 1) / (L * kc);
-        er_steps[s] = (mr + L - 1) / L;
+        er_mask[s] = mask;
     }
-    P->slice_meta.assign((size_t)ns * 4, 0);
-    int64_t eoff = 0, roff = 0;
+    P->ell_meta.assign((size_t)ns * 4, 0);
+    int64_t eoff = 0;
     for (int32_t s = 0; s < ns; ++s) {
-        if (eoff > UINT32_MAX || roff > UINT32_MAX || ell_steps[s] > UINT32_MAX)
-            return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in one part");
-        P->slice_meta[4 * s + 0] = (uint32_t)eoff;
-        P->slice_meta[4 * s + 1] = (uint32_t)ell_steps[s];
-        P->slice_meta[4 * s + 2] = (uint32_t)roff;
-        P->slice_meta[4 * s + 3] = (uint32_t)er_steps[s];
+        if (eoff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the ELL part");
+        P->ell_meta[4 * (size_t)s + 0] = (uint32_t)eoff;
+        P->ell_meta[4 * (size_t)s + 1] = (uint32_t)ell_steps[s];
+        P->ell_meta[4 * (size_t)s + 2] = (uint32_t)(er_mask[s] & 0xFFFFFFFFu);
+        P->ell_meta[4 * (size_t)s + 3] = (uint32_t)(er_mask[s] >> 32);
         eoff += ell_steps[s] * kWave * kc;
-        roff += er_steps[s] * kWave;
     }
-    if (eoff > UINT32_MAX || roff > UINT32_MAX)
-        return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in one part");
+    if (eoff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the ELL part");
+    // residual slices
+    const int32_t nes = P->ner_slices;
+    P->er_meta.assign((size_t)nes * 2, 0);
+    int64_t roff = 0;
+    {
+        std::vector<int32_t> er_steps(nes, 0);
+        for (int32_t p = 0; p < nparts; ++p) {
+            const int32_t ps = P->part_start[p];
+            for (int32_t e = P->er_slice_start[p]; e < P->er_slice_start[p + 1]; ++e) {
+                int32_t mr = 0;
+                for (int32_t r = 0; r < C; ++r) {
+                    const uint16_t lr = P->er_row[(size_t)e * C + r];
+                    if (lr != 0xFFFF) mr = std::max(mr, P->row_er_len[ps + lr]);
+                }
+                er_steps[e] = (mr + L - 1) / L;
+            }
+        }
+        for (int32_t e = 0; e < nes; ++e) {
+            if (roff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the residual part");
+            P->er_meta[2 * (size_t)e + 0] = (uint32_t)roff;
+            P->er_meta[2 * (size_t)e + 1] = (uint32_t)er_steps[e];
+            roff += (int64_t)er_steps[e] * kWave;
+        }
+    }
+    if (roff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the residual part");
     P->ell_slots = eoff;
     P->er_slots = roff;
     const int vb = P->vbytes, dt = P->value_dtype;
@@ -353,7 +424,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
             const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
             const int32_t r0 = ps + (s - P->slice_start[p]) * C;
             const int32_t r1 = std::min(r0 + C, pe);
-            const int64_t eo = P->slice_meta[4 * s + 0], ro = P->slice_meta[4 * s + 2];
+            const int64_t eo = P->ell_meta[4 * (size_t)s + 0];
             for (int32_t row = r0; row < r1; ++row) {
                 const int32_t r = row - r0;
                 const int32_t old = P->perm[row];
@@ -363,19 +434,18 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                 std::sort(ent.begin(), ent.end());
                 int32_t k1 = 0, k2 = 0;
                 const int32_t ell_len = P->row_ell_len[row];
+                const int32_t ep = P->er_pos[row];
+                const int64_t ro = ep >= 0 ? (int64_t)P->er_meta[2 * (size_t)(ep / C)] : 0;
+                const int32_t rr = ep >= 0 ? ep % C : 0;
                 for (const auto& pr : ent) {
                     const int32_t nc = pr.first;
                     const double v = A->val[pr.second];
                     if (nc >= ps && nc < pe && k1 < ell_len) {
-                        const int32_t k = k1++;
-                        const int64_t t = k / (L * kc), u = (k / kc) % L, c = k % kc;
-                        const int64_t slot = eo + (t * kWave + r * L + u) * kc + c;
+                        const int64_t slot = ell_slot_of(eo, k1++, r, L, kc);
                         store_value(&P->ell_val[(size_t)slot * vb], vb, dt, v);
                         P->ell_col[slot] = (uint16_t)(nc - ps);
                     } else {
-                        const int32_t k = k2++;
-                        const int64_t t = k / L, u = k % L;
-                        const int64_t slot = ro + t * kWave + r * L + u;
+                        const int64_t slot = er_slot_of(ro, k2++, rr, L);
                         store_value(&P->er_val[(size_t)slot * vb], vb, dt, v);
                         P->er_col[slot] = nc;
                     }
@@ -399,7 +469,7 @@ extern "C" {
 
 const char* ehyb_last_error(void) { return g_last_error.c_str(); }
 
-const char* ehyb_version(void) { return "0.1.0"; }
+const char* ehyb_version(void) { return "0.2.0"; }
 
 ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, ehyb_plan** out) {
     try {
@@ -438,11 +508,13 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
         P->C = prm.rows_per_wave;
         P->L = kWave / prm.rows_per_wave;
         P->kc = kEllKC;
-        const int64_t max_rows = std::min<int64_t>(65536, prm.lds_bytes / P->xbytes);
-        if (max_rows < 1) return fail(EHYB_EINVAL, "lds_bytes smaller than one x element");
+        // LDS per partition row: its x element and its residual accumulator
+        const int64_t tau = 2 * (int64_t)P->xbytes;
+        const int64_t max_rows = std::min<int64_t>(65535, prm.lds_bytes / tau);
+        if (max_rows < 1) return fail(EHYB_EINVAL, "lds_bytes smaller than one partition row");
         // Eq. 1-2: smallest K with n*tau/(K*P) < SHM, VecSize = ceil(n/(K*P))
         int64_t K = 1;
-        while (n * P->xbytes >= (int64_t)prm.lds_bytes * K * prm.num_cus) ++K;
+        while (n * tau >= (int64_t)prm.lds_bytes * K * prm.num_cus) ++K;
         P->eq1_K = (int32_t)K;
         const int64_t vec = n > 0 ? (n + K * prm.num_cus - 1) / (K * prm.num_cus) : 0;
         if (prm.slice_rows == 0)
@@ -450,7 +522,7 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
                 1, std::min<int64_t>(max_rows, std::max<int64_t>(vec, std::min<int64_t>(n, 512))));
         if (prm.slice_rows < 1) return fail(EHYB_EINVAL, "slice_rows must be >= 1");
         if (prm.slice_rows > max_rows)
-            return fail(EHYB_EINVAL, "slice_rows x-slice exceeds the LDS budget or 2^16 rows");
+            return fail(EHYB_EINVAL, "slice_rows exceeds the LDS budget (2 * x bytes per row) or 65535 rows");
         const int64_t cap = std::min<int64_t>(max_rows, prm.slice_rows + (int64_t)prm.slice_rows * prm.imbalance_pct / 100);
         const int32_t nparts_req = n > 0 ? (int32_t)((n + prm.slice_rows - 1) / prm.slice_rows) : 0;
         P->params = prm;
@@ -497,6 +569,7 @@ ehyb_status ehyb_plan_stats_get(const ehyb_plan* P, ehyb_plan_stats* out) {
     out->algorithmic_bytes = algorithmic_bytes(*P);
     out->nparts = P->nparts;
     out->nslices = P->nslices;
+    out->ner_slices = P->ner_slices;
     out->slice_rows = P->params.slice_rows;
     out->max_part_rows = P->max_part_rows;
     out->rows_per_slice = P->C;
@@ -517,6 +590,7 @@ ehyb_status ehyb_plan_arrays_get(const ehyb_plan* P, ehyb_plan_arrays* out) {
     out->n = P->n;
     out->nparts = P->nparts;
     out->nslices = P->nslices;
+    out->ner_slices = P->ner_slices;
     out->lanes_per_row = P->L;
     out->kc = P->kc;
     out->value_dtype = P->value_dtype;
@@ -525,7 +599,10 @@ ehyb_status ehyb_plan_arrays_get(const ehyb_plan* P, ehyb_plan_arrays* out) {
     out->perm = P->perm.data();
     out->part_start = P->part_start.data();
     out->slice_start = P->slice_start.data();
-    out->slice_meta = P->slice_meta.data();
+    out->er_slice_start = P->er_slice_start.data();
+    out->ell_meta = P->ell_meta.data();
+    out->er_meta = P->er_meta.data();
+    out->er_row = P->er_row.data();
     out->ell_val = P->ell_val.data();
     out->ell_col = P->ell_col.data();
     out->er_val = P->er_val.data();
@@ -545,31 +622,28 @@ ehyb_status ehyb_plan_decode_csr(const ehyb_plan* P, int64_t* row_ptr, int32_t* 
     for (int32_t p = 0; p < P->nparts; ++p) {
         const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
         for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
-            const int64_t eo = P->slice_meta[4 * s + 0], ro = P->slice_meta[4 * s + 2];
+            const int64_t eo = P->ell_meta[4 * (size_t)s + 0];
             const int32_t r0 = ps + (s - P->slice_start[p]) * C;
             for (int32_t r = 0; r < C && r0 + r < pe; ++r) {
                 const int32_t row = r0 + r;
                 int64_t out_at = row_ptr[row];
                 int32_t a = 0, b = 0;
                 const int32_t na = P->row_ell_len[row], nb = P->row_er_len[row];
-                auto ell_slot = [&](int32_t k) {
-                    const int64_t t = k / (L * kc), u = (k / kc) % L, c = k % kc;
-                    return eo + (t * kWave + r * L + u) * kc + c;
-                };
-                auto er_slot = [&](int32_t k) {
-                    const int64_t t = k / L, u = k % L;
-                    return ro + t * kWave + r * L + u;
-                };
+                const int32_t ep = P->er_pos[row];
+                const int64_t ro = ep >= 0 ? (int64_t)P->er_meta[2 * (size_t)(ep / C)] : 0;
+                const int32_t rr = ep >= 0 ? ep % C : 0;
                 while (a < na || b < nb) {
-                    const int32_t ca = a < na ? ps + P->ell_col[ell_slot(a)] : INT32_MAX;
-                    const int32_t cb = b < nb ? P->er_col[er_slot(b)] : INT32_MAX;
+                    const int64_t sa = a < na ? ell_slot_of(eo, a, r, L, kc) : 0;
+                    const int64_t sb = b < nb ? er_slot_of(ro, b, rr, L) : 0;
+                    const int32_t ca = a < na ? ps + P->ell_col[sa] : INT32_MAX;
+                    const int32_t cb = b < nb ? P->er_col[sb] : INT32_MAX;
                     if (ca < cb) {
                         col_idx[out_at] = ca;
-                        val[out_at] = load_value(&P->ell_val[(size_t)ell_slot(a) * vb], dt);
+                        val[out_at] = load_value(&P->ell_val[(size_t)sa * vb], dt);
                         ++a;
                     } else {
                         col_idx[out_at] = cb;
-                        val[out_at] = load_value(&P->er_val[(size_t)er_slot(b) * vb], dt);
+                        val[out_at] = load_value(&P->er_val[(size_t)sb * vb], dt);
                         ++b;
                     }
                     ++out_at;
@@ -591,13 +665,13 @@ void ehyb_plan_destroy(ehyb_plan* P) { delete P; }
 }  // extern "C"
 
 // ------------------------------------------------------------- plan files
-// Layout: magic "EHYBPLN1", u32 version, then fixed header fields and arrays
+// Layout: magic "EHYBPLN2", u32 version, then fixed header fields and arrays
 // (each prefixed by its u64 byte length), then a u64 FNV-1a checksum of all
 // preceding bytes.
 
 namespace {
-const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '1'};
-const uint32_t kVersion = 1;
+const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '2'};
+const uint32_t kVersion = 2;
 
 uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
     for (size_t i = 0; i < n; ++i) {
@@ -645,6 +719,59 @@ struct Reader {
         raw(v.data(), b);
     }
 };
+
+// Every bound a kernel relies on, checked on a loaded plan.
+const char* validate_loaded(const ehyb_plan& P) {
+    const size_t n = (size_t)P.n;
+    const int C = P.C;
+    if (P.perm.size() != n || P.part_start.size() != (size_t)P.nparts + 1 ||
+        P.slice_start.size() != (size_t)P.nparts + 1 || P.er_slice_start.size() != (size_t)P.nparts + 1 ||
+        P.ell_meta.size() != (size_t)P.nslices * 4 || P.er_meta.size() != (size_t)P.ner_slices * 2 ||
+        P.er_row.size() != (size_t)P.ner_slices * C ||
+        P.ell_val.size() != (size_t)P.ell_slots * P.vbytes || P.ell_col.size() != (size_t)P.ell_slots ||
+        P.er_val.size() != (size_t)P.er_slots * P.vbytes || P.er_col.size() != (size_t)P.er_slots ||
+        P.row_ell_len.size() != n || P.row_er_len.size() != n)
+        return "plan file array sizes are inconsistent";
+    if (P.nparts > 0 && (P.part_start[0] != 0 || P.part_start[P.nparts] != (int32_t)n || P.slice_start[0] != 0 ||
+                         P.slice_start[P.nparts] != P.nslices || P.er_slice_start[0] != 0 ||
+                         P.er_slice_start[P.nparts] != P.ner_slices))
+        return "plan file partition bounds are inconsistent";
+    if (P.nparts == 0 && n != 0) return "plan file has rows but no partitions";
+    const int64_t max_rows = std::min<int64_t>(65535, (int64_t)(160 * 1024) / (2 * P.xbytes));
+    for (int32_t p = 0; p < P.nparts; ++p) {
+        const int64_t sz = (int64_t)P.part_start[p + 1] - P.part_start[p];
+        const int64_t sl = (int64_t)P.slice_start[p + 1] - P.slice_start[p];
+        const int64_t el = (int64_t)P.er_slice_start[p + 1] - P.er_slice_start[p];
+        if (sz <= 0 || sz > max_rows || sl != (sz + C - 1) / C || el < 0 || el > sl)
+            return "plan file partition sizes are inconsistent";
+        for (int32_t s = P.slice_start[p]; s < P.slice_start[p + 1]; ++s) {
+            const uint64_t eo = P.ell_meta[4 * (size_t)s], es = P.ell_meta[4 * (size_t)s + 1];
+            if (eo + es * kWave * P.kc > (uint64_t)P.ell_slots) return "plan file ELL slot range out of bounds";
+            for (uint64_t q = eo; q < eo + es * kWave * P.kc; ++q)
+                if (P.ell_col[q] >= sz) return "plan file ELL column outside its slice";
+            const uint64_t mask = (uint64_t)P.ell_meta[4 * (size_t)s + 2] | ((uint64_t)P.ell_meta[4 * (size_t)s + 3] << 32);
+            const int64_t rows = std::min<int64_t>(C, sz - (int64_t)(s - P.slice_start[p]) * C);
+            if (rows < 64 && (mask >> rows) != 0) return "plan file residual mask names a missing row";
+        }
+        for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e) {
+            const uint64_t ro = P.er_meta[2 * (size_t)e], rs = P.er_meta[2 * (size_t)e + 1];
+            if (ro + rs * kWave > (uint64_t)P.er_slots) return "plan file residual slot range out of bounds";
+            for (int r = 0; r < C; ++r) {
+                const uint16_t lr = P.er_row[(size_t)e * C + r];
+                if (lr != 0xFFFF && lr >= sz) return "plan file residual row outside its partition";
+            }
+        }
+    }
+    for (size_t s = 0; s < P.er_col.size(); ++s)
+        if (P.er_col[s] < 0 || (size_t)P.er_col[s] >= n) return "plan file residual column out of range";
+    std::vector<char> seen(n, 0);
+    for (size_t i = 0; i < n; ++i) {
+        const int32_t o = P.perm[i];
+        if (o < 0 || (size_t)o >= n || seen[o]) return "plan file permutation is invalid";
+        seen[o] = 1;
+    }
+    return nullptr;
+}
 }  // namespace
 
 extern "C" {
@@ -663,6 +790,7 @@ ehyb_status ehyb_plan_save(const ehyb_plan* P, const char* path) {
         w.pod(P->kc);
         w.pod(P->nparts);
         w.pod(P->nslices);
+        w.pod(P->ner_slices);
         w.pod(P->value_dtype);
         w.pod(P->eq1_K);
         w.pod(P->max_part_rows);
@@ -674,7 +802,10 @@ ehyb_status ehyb_plan_save(const ehyb_plan* P, const char* path) {
         w.vec(P->perm);
         w.vec(P->part_start);
         w.vec(P->slice_start);
-        w.vec(P->slice_meta);
+        w.vec(P->er_slice_start);
+        w.vec(P->ell_meta);
+        w.vec(P->er_meta);
+        w.vec(P->er_row);
         w.vec(P->ell_val);
         w.vec(P->ell_col);
         w.vec(P->er_val);
@@ -725,6 +856,7 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.pod(P->kc);
         r.pod(P->nparts);
         r.pod(P->nslices);
+        r.pod(P->ner_slices);
         r.pod(P->value_dtype);
         r.pod(P->eq1_K);
         r.pod(P->max_part_rows);
@@ -733,9 +865,9 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.pod(P->nnz_ell);
         r.pod(P->nnz_er);
         r.pod(P->n_er_rows);
-        if (!r.ok || P->n < 0 || P->n > INT32_MAX || P->nparts < 0 || P->nslices < 0 ||
+        if (!r.ok || P->n < 0 || P->n > INT32_MAX || P->nparts < 0 || P->nslices < 0 || P->ner_slices < 0 ||
             P->value_dtype < 0 || P->value_dtype > 2 || P->L < 1 || P->L > kWave || P->C * P->L != kWave ||
-            P->kc != kEllKC || P->ell_slots < 0 || P->er_slots < 0)
+            P->kc != kEllKC || P->ell_slots < 0 || P->er_slots < 0 || P->max_part_rows < 0)
             return fail(EHYB_EINVAL, "plan file header is inconsistent");
         P->vbytes = P->value_dtype == EHYB_F64 ? 8 : (P->value_dtype == EHYB_F32 ? 4 : 2);
         P->xbytes = P->value_dtype == EHYB_F64 ? 8 : 4;
@@ -743,7 +875,10 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.vec(P->perm, lim);
         r.vec(P->part_start, lim);
         r.vec(P->slice_start, lim);
-        r.vec(P->slice_meta, lim);
+        r.vec(P->er_slice_start, lim);
+        r.vec(P->ell_meta, lim);
+        r.vec(P->er_meta, lim);
+        r.vec(P->er_row, lim);
         r.vec(P->ell_val, lim);
         r.vec(P->ell_col, lim);
         r.vec(P->er_val, lim);
@@ -751,49 +886,13 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.vec(P->row_ell_len, lim);
         r.vec(P->row_er_len, lim);
         if (!r.ok || r.at != r.n) return fail(EHYB_EINVAL, "plan file body is malformed");
-        const size_t n = (size_t)P->n;
-        if (P->perm.size() != n || P->part_start.size() != (size_t)P->nparts + 1 ||
-            P->slice_start.size() != (size_t)P->nparts + 1 || P->slice_meta.size() != (size_t)P->nslices * 4 ||
-            P->ell_val.size() != (size_t)P->ell_slots * P->vbytes || P->ell_col.size() != (size_t)P->ell_slots ||
-            P->er_val.size() != (size_t)P->er_slots * P->vbytes || P->er_col.size() != (size_t)P->er_slots ||
-            P->row_ell_len.size() != n || P->row_er_len.size() != n)
-            return fail(EHYB_EINVAL, "plan file array sizes are inconsistent");
-        // bounds that the kernels rely on
-        if (P->nparts > 0 && (P->part_start[0] != 0 || P->part_start[P->nparts] != (int32_t)n ||
-                              P->slice_start[0] != 0 || P->slice_start[P->nparts] != P->nslices))
-            return fail(EHYB_EINVAL, "plan file partition bounds are inconsistent");
-        for (int32_t p = 0; p < P->nparts; ++p) {
-            const int64_t sz = (int64_t)P->part_start[p + 1] - P->part_start[p];
-            const int64_t sl = (int64_t)P->slice_start[p + 1] - P->slice_start[p];
-            if (sz <= 0 || sz > 65536 || sz * P->xbytes > 160 * 1024 || sl != (sz + P->C - 1) / P->C)
-                return fail(EHYB_EINVAL, "plan file partition sizes are inconsistent");
-            for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
-                const uint64_t eo = P->slice_meta[4 * s], es = P->slice_meta[4 * s + 1];
-                const uint64_t ro = P->slice_meta[4 * s + 2], rs = P->slice_meta[4 * s + 3];
-                if (eo + es * kWave * P->kc > (uint64_t)P->ell_slots || ro + rs * kWave > (uint64_t)P->er_slots)
-                    return fail(EHYB_EINVAL, "plan file slot ranges are out of bounds");
-            }
-        }
-        // every stored column must be valid for the kernels' gathers
-        for (size_t s = 0; s < P->er_col.size(); ++s)
-            if (P->er_col[s] < 0 || (size_t)P->er_col[s] >= n)
-                return fail(EHYB_EINVAL, "plan file residual column out of range");
-        std::vector<char> seen(n, 0);
-        for (size_t i = 0; i < n; ++i) {
-            const int32_t o = P->perm[i];
-            if (o < 0 || (size_t)o >= n || seen[o]) return fail(EHYB_EINVAL, "plan file permutation is invalid");
-            seen[o] = 1;
-        }
-        P->iperm.resize(n);
-        for (size_t i = 0; i < n; ++i) P->iperm[P->perm[i]] = (int32_t)i;
-        for (int32_t p = 0; p < P->nparts; ++p) {
-            const int32_t sz = P->part_start[p + 1] - P->part_start[p];
-            for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
-                const uint64_t eo = P->slice_meta[4 * s], es = P->slice_meta[4 * s + 1];
-                for (uint64_t q = eo; q < eo + es * kWave * P->kc; ++q)
-                    if (P->ell_col[q] >= sz) return fail(EHYB_EINVAL, "plan file ELL column outside its slice");
-            }
-        }
+        if (const char* why = validate_loaded(*P)) return fail(EHYB_EINVAL, why);
+        int32_t maxp = 0;
+        for (int32_t p = 0; p < P->nparts; ++p) maxp = std::max(maxp, P->part_start[p + 1] - P->part_start[p]);
+        if (maxp != P->max_part_rows) return fail(EHYB_EINVAL, "plan file largest partition is inconsistent");
+        P->iperm.resize((size_t)P->n);
+        for (size_t i = 0; i < (size_t)P->n; ++i) P->iperm[P->perm[i]] = (int32_t)i;
+        build_er_pos(*P);
         *out = P.release();
         return EHYB_OK;
     } catch (const std::bad_alloc&) {

@@ -38,7 +38,8 @@ Error partition_multilevel(const Graph& g, int32_t nparts, int64_t cap, uint64_t
 
 // Byte offsets of each array inside the device blob.
 struct BlobLayout {
-    size_t part_start = 0, slice_start = 0, slice_meta = 0;
+    size_t part_start = 0, slice_start = 0, er_slice_start = 0;
+    size_t ell_meta = 0, er_meta = 0, er_row = 0;
     size_t ell_val = 0, ell_col = 0, er_val = 0, er_col = 0;
     size_t perm = 0, xp = 0, yp = 0;
     size_t total = 0;
@@ -50,25 +51,30 @@ struct ehyb_plan {
     int64_t n = 0, nnz = 0;
     ehyb_params params{};          // resolved parameters
     int32_t L = 1, C = 64, kc = ehyb::kEllKC;
-    int32_t nparts = 0, nslices = 0;
+    int32_t nparts = 0, nslices = 0, ner_slices = 0;
     int32_t value_dtype = EHYB_F64;
     int32_t vbytes = 8;            // bytes per stored value
     int32_t xbytes = 8;            // bytes per x element
     int32_t eq1_K = 1;
     int32_t max_part_rows = 0;
-    std::vector<int32_t> perm;         // new -> old
-    std::vector<int32_t> iperm;        // old -> new (the reorder table)
-    std::vector<int32_t> part_start;   // [nparts+1]
-    std::vector<int32_t> slice_start;  // [nparts+1]
-    std::vector<uint32_t> slice_meta;  // [4*nslices]
-    std::vector<unsigned char> ell_val;  // ell_slots * vbytes
-    std::vector<uint16_t> ell_col;       // ell_slots
-    std::vector<unsigned char> er_val;   // er_slots * vbytes
-    std::vector<int32_t> er_col;         // er_slots
+    std::vector<int32_t> perm;            // new -> old
+    std::vector<int32_t> iperm;           // old -> new (the reorder table)
+    std::vector<int32_t> part_start;      // [nparts+1]
+    std::vector<int32_t> slice_start;     // [nparts+1] ELL slices
+    std::vector<int32_t> er_slice_start;  // [nparts+1] residual slices
+    std::vector<uint32_t> ell_meta;       // [4*nslices] off, steps, er mask lo, hi
+    std::vector<uint32_t> er_meta;        // [2*ner_slices] off, steps
+    std::vector<uint16_t> er_row;         // [C*ner_slices] local row, 0xFFFF = none
+    std::vector<int32_t> er_pos;          // [n] permuted row -> e*C + r in the residual part, -1
+    std::vector<unsigned char> ell_val;   // ell_slots * vbytes
+    std::vector<uint16_t> ell_col;        // ell_slots
+    std::vector<unsigned char> er_val;    // er_slots * vbytes
+    std::vector<int32_t> er_col;          // er_slots
     std::vector<int32_t> row_ell_len, row_er_len;  // [n], permuted rows
     int64_t ell_slots = 0, er_slots = 0;
     int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0;
     double t_graph = 0, t_partition = 0, t_reorder = 0, t_encode = 0;
+    int32_t launch_waves = 0;      // 0 = automatic launch shape
     // device binding (non-owning)
     void* dev_blob = nullptr;
     size_t dev_bytes = 0;

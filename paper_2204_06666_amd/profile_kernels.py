@@ -1,0 +1,51 @@
+"""Fixed kernel sequence for hardware-counter runs (rocprofv3 --pmc).
+
+Runs the headline EHYB FP64 product `--reps` times and the copy probe on a
+buffer of known size `--reps` times, nothing else on the GPU, so that the
+per-dispatch FETCH_SIZE / WRITE_SIZE of each kernel can be read off and the
+EHYB counters scaled by what the same counters report for the copy of a known
+number of bytes.
+
+    rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch -- python3 paper_2204_06666_amd/profile_kernels.py
+"""
+import argparse
+import os
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=256)
+    args = ap.parse_args()
+    import torch
+
+    import matgen
+    from paper_2204_06666_amd import Plan, probe_copy
+    from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS
+
+    dev = torch.device("cuda:0")
+    A = matgen.config_matrix(HEADLINE["config"])
+    x = matgen.uniform_vector(A.n_rows, HEADLINE["x_seed"])
+    plan = Plan(A, **HEADLINE_PARAMS).upload(dev)
+    st = plan.stats()
+    xp = torch.from_numpy(x[plan.perm()]).to(dev)
+    yp = torch.empty_like(xp)
+    src = torch.ones((args.copy_mib << 20) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        plan.spmv(xp, yp)
+    torch.cuda.synchronize()
+    for _ in range(args.reps):
+        probe_copy(src, dst)
+    torch.cuda.synchronize()
+    print(f"ehyb algorithmic_bytes={st['algorithmic_bytes']} copy_bytes_read={src.numel() * 4} "
+          f"copy_bytes_written={dst.numel() * 4} reps={args.reps}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

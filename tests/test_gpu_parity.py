@@ -71,7 +71,7 @@ CASES = [
                                          explicit_zeros=20, negative_zero=True), {"slice_rows": 70}),
     ("natural-order", lambda: matgen.stencil3d(24, points=7, val_seed=3), {"slice_rows": 1000, "partitioner": 1}),
     ("width-cap", lambda: matgen.stencil3d(20, perm_seed=1, val_seed=2), {"slice_rows": 900, "ell_width_cap": 7}),
-    ("max-slice", lambda: matgen.stencil3d(30, perm_seed=8, val_seed=9), {"slice_rows": 19800, "imbalance_pct": 3}),
+    ("max-slice", lambda: matgen.stencil3d(30, perm_seed=8, val_seed=9), {"slice_rows": 9900, "imbalance_pct": 3}),
 ]
 
 

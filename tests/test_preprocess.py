@@ -13,7 +13,7 @@ from oracle.structure import check_plan, layout_spmv
 from paper_2204_06666_amd import EhybError, Plan, _abi
 
 
-def _full_check(A, plan, value_dtype=np.float64, width_cap=0, x_seed=7, tau_x=8):
+def _full_check(A, plan, value_dtype=np.float64, width_cap=0, x_seed=7, tau_x=16):
     v = plan.arrays()
     st = check_plan(A, v, width_cap=width_cap, value_dtype=value_dtype, tau_x=tau_x)
     perm = v["perm"]
@@ -94,7 +94,8 @@ def test_partitioner_beats_scrambled_blocks():
 def test_eq1_default_slice_rows():
     A = matgen.stencil3d(100, points=7)   # n = 1e6
     n = A.n_rows
-    K, vec = oracle.eq1_rule(n, 8, 256, 160 * 1024)
+    # tau = 16: each partition row keeps its x element and a residual accumulator
+    K, vec = oracle.eq1_rule(n, 16, 256, 160 * 1024)
     P = Plan(A, partitioner=1)
     s = P.stats()
     assert s["eq1_K"] == K and s["slice_rows"] == vec == 3907
@@ -116,7 +117,7 @@ def test_determinism_same_seed():
     A = matgen.stencil3d(14, perm_seed=2, val_seed=3)
     a = Plan(A, slice_rows=400, seed=5).arrays()
     b = Plan(A, slice_rows=400, seed=5).arrays()
-    for k in ("perm", "part_start", "ell_val", "ell_col", "er_col", "slice_meta"):
+    for k in ("perm", "part_start", "ell_val", "ell_col", "er_col", "ell_meta", "er_meta", "er_row"):
         assert np.array_equal(a[k], b[k]), k
 
 
@@ -137,7 +138,7 @@ def test_tiny_and_empty():
 def test_fp32_plan_values_rounded():
     A = matgen.stencil3d(10, perm_seed=1, val_seed=2)
     P = Plan(A, slice_rows=300, value_dtype=1)
-    _full_check(A, P, value_dtype=np.float32, tau_x=4)
+    _full_check(A, P, value_dtype=np.float32, tau_x=8)
 
 
 @pytest.mark.parametrize("mutate,status", [
@@ -164,7 +165,7 @@ def test_row_ptr_inconsistent():
     assert e.value.status == _abi.EHYB_EINVAL
 
 
-@pytest.mark.parametrize("kw", [{"slice_rows": 20481}, {"rows_per_wave": 3}, {"rows_per_wave": 128},
+@pytest.mark.parametrize("kw", [{"slice_rows": 10241}, {"rows_per_wave": 3}, {"rows_per_wave": 128},
                                 {"value_dtype": 7}, {"lds_bytes": 200000}, {"imbalance_pct": -1},
                                 {"partitioner": 5}, {"ell_width_cap": -2}])
 def test_invalid_params_rejected(kw):
@@ -218,8 +219,8 @@ def test_algorithmic_bytes_formula():
     A = matgen.stencil3d(12, perm_seed=1, val_seed=2)
     P = Plan(A, slice_rows=400)
     s = P.stats()
-    want = (s["ell_slots"] * 10 + s["er_slots"] * 12 + s["nslices"] * 16 + (s["nparts"] + 1) * 8
-            + 2 * s["n"] * 8)
+    want = (s["ell_slots"] * 10 + s["er_slots"] * 12 + s["nslices"] * 16
+            + s["ner_slices"] * (8 + 2 * s["rows_per_slice"]) + (s["nparts"] + 1) * 12 + 2 * s["n"] * 8)
     assert s["algorithmic_bytes"] == want
 
 
@@ -227,6 +228,6 @@ def test_host_threads_do_not_change_the_plan():
     A = matgen.stencil3d(14, perm_seed=4, val_seed=5)
     a = Plan(A, slice_rows=500, n_threads=1).arrays()
     b = Plan(A, slice_rows=500, n_threads=4).arrays()
-    for k in ("perm", "ell_val", "ell_col", "er_val", "er_col", "slice_meta"):
+    for k in ("perm", "ell_val", "ell_col", "er_val", "er_col", "ell_meta", "er_meta", "er_row"):
         assert np.array_equal(a[k], b[k]), k
     assert os.environ.get("OMP_NUM_THREADS", "") == os.environ.get("OMP_NUM_THREADS", "")

@@ -24,13 +24,17 @@ def _tiny():
     for slot, v, c in [(0, 1, 0), (1, 2, 1), (2, 4, 0), (3, 5, 1),
                        (128, 6, 0), (129, 7, 1), (130, 9, 0), (131, 10, 1)]:
         ell_val[slot], ell_col[slot] = v, c
+    # residual rows: partition 0 -> local row 0; partition 1 -> local row 1
     er_val = np.zeros(128)
     er_col = np.zeros(128, dtype=np.int32)
     er_val[0], er_col[0] = 3, 3
-    er_val[65], er_col[65] = 8, 0
+    er_val[64], er_col[64] = 8, 0
+    er_row = np.full((2, 64), 0xFFFF, dtype=np.uint16)
+    er_row[0, 0], er_row[1, 0] = 0, 1
     view = dict(n=4, nparts=2, L=1, kc=2, perm=np.arange(4), part_start=np.array([0, 2, 4]),
-                slice_start=np.array([0, 1, 2]),
-                slice_meta=np.array([[0, 1, 0, 1], [128, 1, 64, 1]], dtype=np.uint32),
+                slice_start=np.array([0, 1, 2]), er_slice_start=np.array([0, 1, 2]),
+                ell_meta=np.array([[0, 1, 0b01, 0], [128, 1, 0b10, 0]], dtype=np.uint32),
+                er_meta=np.array([[0, 1], [64, 1]], dtype=np.uint32), er_row=er_row,
                 ell_val=ell_val, ell_col=ell_col, er_val=er_val, er_col=er_col,
                 row_ell_len=np.array([2, 2, 2, 2]), row_er_len=np.array([1, 0, 0, 1]))
     return A, d, view
@@ -49,10 +53,13 @@ def test_hand_built_plan_passes():
     (lambda v: v["ell_val"].__setitem__(7, 1.0), "padding"),
     (lambda v: v["ell_val"].__setitem__(7, -0.0), "padding"),
     (lambda v: v["ell_col"].__setitem__(1, 3), "outside"),
-    (lambda v: v["er_col"].__setitem__(65, 1), "pattern differs"),
+    (lambda v: v["er_col"].__setitem__(64, 1), "pattern differs"),
     (lambda v: v["perm"].__setitem__(slice(0, 2), [1, 0]), ""),
     (lambda v: v["row_er_len"].__setitem__(0, 0), ""),
-    (lambda v: v["slice_meta"].__setitem__((1, 0), 0), "overlapping"),
+    (lambda v: v["ell_meta"].__setitem__((1, 0), 0), "overlapping"),
+    (lambda v: v["ell_meta"].__setitem__((0, 2), 0), "mask"),
+    (lambda v: v["er_row"].__setitem__((1, 0), 0), ""),
+    (lambda v: v["er_meta"].__setitem__((1, 1), 2), ""),
     (lambda v: v["part_start"].__setitem__(1, 3), ""),
 ])
 def test_planted_mistakes_are_caught(mutate, msg):
@@ -66,15 +73,16 @@ def test_planted_mistakes_are_caught(mutate, msg):
 def test_intra_partition_entry_in_residual_is_caught():
     """Move ELL entry (1,0) into the residual part: same content, wrong class."""
     A, _, view = _tiny()
-    view["ell_val"][2], view["ell_val"][3] = 5, 0      # row 1 keeps only (1,1) ... shifted
+    view["ell_val"][2], view["ell_val"][3] = 5, 0      # row 1 keeps only (1,1) in ELL
     view["ell_col"][2], view["ell_col"][3] = 1, 0
     view["row_ell_len"][1] = 1
     view["row_er_len"][1] = 1
+    view["er_row"][0, 1] = 1                            # residual slice 0: rows 0, 1
     view["er_val"][1], view["er_col"][1] = 4, 0
+    view["ell_meta"][0, 2] = 0b11
     with pytest.raises(PlanError, match="intra-partition"):
         check_plan(A, view)
-    # the same encoding is valid under a width cap of 1 for row 1 only if every
-    # row respects the cap, which rows 0, 2, 3 do not
+    # a width cap of 1 would need every ELL row to respect it, which rows 0, 2, 3 do not
     with pytest.raises(PlanError):
         check_plan(A, view, width_cap=1)
 
