@@ -90,16 +90,22 @@ typedef struct {
                                two in [1, 64]; 64/rows_per_wave lanes share a
                                row. 0 = 64 (one lane per row) */
     int32_t value_dtype;    /* ehyb_dtype; 0 = EHYB_F64 */
-    int32_t lds_bytes;      /* LDS budget per workgroup; 0 = 160 KiB.  Each
-                               partition row holds its x element and a
-                               residual accumulator there (tau = 2 * bytes of
-                               an x element in Eq. 1) */
+    int32_t lds_bytes;      /* LDS budget per workgroup; 0 = 160 KiB.  It
+                               holds the x-slice, the halo and one residual
+                               accumulator per row; Eq. 1 reserves two
+                               elements per row (tau = 2 * bytes of an x
+                               element) */
     int32_t num_cus;        /* P in Eq. 1; 0 = 256 */
     int32_t n_threads;      /* host threads; 0 = all available */
     int32_t imbalance_pct;  /* allowed overfill of a partition above
                                slice_rows, percent; 0 = 3 */
     int32_t partitioner;    /* ehyb_partitioner; 0 = multilevel */
-    int32_t reserved;       /* must be 0 */
+    int32_t halo_rows;      /* neighbour x entries cached per partition in LDS
+                               next to its x-slice (the "halo"): 0 = as many
+                               as the LDS budget leaves, > 0 = at most that
+                               many, -1 = none, so that every entry outside the
+                               partition goes to the residual part (the
+                               paper's split) */
     uint64_t seed;          /* partitioner seed (deterministic for a seed) */
 } ehyb_params;
 
@@ -109,6 +115,8 @@ typedef struct {
     int64_t ell_slots;        /* ELL slots including padding */
     int64_t er_slots;         /* residual slots including padding */
     int64_t n_er_rows;        /* rows with at least one residual entry */
+    int64_t nnz_halo;         /* ELL entries whose column is in the halo */
+    int64_t n_halo;           /* halo entries, all partitions */
     int64_t device_bytes;     /* size of the device blob for ehyb_plan_upload */
     int64_t algorithmic_bytes;/* bytes one permuted-space SpMV must move, each
                                  array element once: ELL and residual slots
@@ -126,6 +134,8 @@ typedef struct {
     int32_t kc;               /* ELL entries per lane per load step */
     int32_t value_dtype;      /* ehyb_dtype */
     int32_t eq1_K;            /* K of Eq. 1 for this n (informational) */
+    int32_t max_halo;         /* largest halo of one partition */
+    int32_t lds_bytes_used;   /* LDS one workgroup of ehyb_spmv uses */
     double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */
 } ehyb_plan_stats;
 
@@ -136,11 +146,22 @@ typedef struct {
  * inside it rows are in non-increasing ELL count.
  *
  * ELL part: partition p's rows are cut into row-slices of C = 64/L rows,
- * slices [slice_start[p], slice_start[p+1]); row r of ELL slice s is local
- * row (s - slice_start[p])*C + r.  ell_meta[4s..4s+3] = slot offset, step
- * count, and a 64-bit mask (low word, high word) whose bit r says that row r
- * also has residual entries.  Columns are offsets into the partition's
- * x-slice (local, 16-bit).
+ * slices [slice_start[p], slice_start[p+1]).  They are stored in the order a
+ * workgroup takes them: first the ell_free[p] slices none of whose rows has
+ * residual entries, then the others, each group by ascending row.
+ * ell_meta[4s..4s+3] = slot offset; step count (low 16 bits) and the slice's
+ * index j within its partition (high 16 bits: row r of the slice is local row
+ * j*C + r); a 64-bit mask (low word, high word) whose bit r says that row r
+ * also has residual entries.  Columns are 16-bit indices into the
+ * partition's LDS vector: c < size of the partition is x-slice element c
+ * (permuted row part_start[p] + c); c >= size is halo element
+ * halo_idx[halo_start[p] + c - size].
+ *
+ * Halo: partition p caches the x entries halo_idx[halo_start[p] ..
+ * halo_start[p+1]) (permuted global indices, ascending, none inside the
+ * partition): entries of the partition's rows whose column is there are
+ * stored in the ELL part, the rest of the out-of-partition entries in the
+ * residual part.
  *
  * Residual part: the rows of partition p with residual entries, sorted by
  * non-increasing residual count (ties by local row), are cut into row-slices
@@ -158,11 +179,14 @@ typedef struct {
 typedef struct {
     int64_t n;
     int32_t nparts, nslices, ner_slices, lanes_per_row, kc, value_dtype;
-    int64_t ell_slots, er_slots;
+    int64_t ell_slots, er_slots, n_halo;
     const int32_t *perm;           /* [n] new index -> original index */
     const int32_t *part_start;     /* [nparts + 1] */
     const int32_t *slice_start;    /* [nparts + 1] first ELL slice of each partition */
     const int32_t *er_slice_start; /* [nparts + 1] first residual slice of each partition */
+    const int32_t *ell_free;       /* [nparts] leading ELL slices without residual rows */
+    const int32_t *halo_start;     /* [nparts + 1] */
+    const int32_t *halo_idx;       /* [n_halo] */
     const uint32_t *ell_meta;      /* [4 * nslices] */
     const uint32_t *er_meta;       /* [2 * ner_slices] */
     const uint16_t *er_row;        /* [C * ner_slices] */

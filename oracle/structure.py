@@ -9,9 +9,10 @@ properties the paper fixes for the format:
 * every partition's slice of x fits the on-chip cache and its local column
   indices fit 16 bits (Section 3.3, Eq. 1-2; Section 3.4, compact index);
 * every stored entry of the ELL part has its column inside the row's own
-  partition, and (with no width cap) every intra-partition entry is in the ELL
-  part, every other entry in the residual ("extra rows") part (Section 3.1-3.2,
-  Alg. 1 classification);
+  partition or in the partition's halo (the out-of-partition x entries it
+  caches next to its x-slice), and (with no width cap) every such entry is in
+  the ELL part, every other entry in the residual ("extra rows") part
+  (Section 3.1-3.2, Alg. 1 classification);
 * within a partition, rows are ordered by non-increasing ELL entry count
   (Section 3.2, post-partitioning reordering), ties broken by original index;
 * padding slots hold +0.0 and a valid column;
@@ -21,7 +22,7 @@ properties the paper fixes for the format:
 Layout rules being checked (row-slice = C = 64 / L rows, one 64-lane
 wavefront per row-slice, L lanes per row, KC consecutive entries per lane per
 step).  ELL part: partition p's rows, in order, cut into row-slices; row r of
-ELL slice s is local row (s - slice_start[p])*C + r.  Residual part: the rows
+an ELL slice with index j is local row j*C + r.  Residual part: the rows
 of partition p that have residual entries, by non-increasing residual count
 (ties by local row), cut into row-slices; row r of residual slice e is local
 row er_row[e, r] (0xFFFF: none).  In either part
@@ -31,9 +32,14 @@ row er_row[e, r] (0xFFFF: none).  In either part
         slot = off + (t*64 + lane)*KC + c,
     with KC = kc in the ELL part and KC = 1 in the residual part.
 
+ELL columns are 16-bit indices into the partition's LDS vector: below the
+partition size an x-slice element, otherwise halo element
+halo_idx[halo_start[p] + c - size].
+
 ``view`` is a mapping with the keys: n, nparts, L, kc, perm, part_start,
-slice_start, er_slice_start, ell_meta (uint32 [nslices, 4]: offset, steps,
-residual-row mask low/high), er_meta (uint32 [ner_slices, 2]: offset, steps),
+halo_start, halo_idx, slice_start, er_slice_start, ell_free, ell_meta (uint32 [nslices, 4]: offset,
+steps | slice index << 16, residual-row mask low/high; slices without residual
+rows first), er_meta (uint32 [ner_slices, 2]: offset, steps),
 er_row (uint16 [ner_slices, C]), ell_val, ell_col (uint16), er_val, er_col
 (int32), row_ell_len, row_er_len.
 """
@@ -70,13 +76,16 @@ def _slice_rows(view, which: str):
     _req((np.diff(starts) >= 0).all(), f"{which} slice bounds decrease")
     part = np.repeat(np.arange(nparts), np.diff(starts))
     if which == "ell":
-        local = (np.arange(ns) - starts[part])[:, None] * C + np.arange(C)[None, :]
+        steps = meta[:, 1] & 0xFFFF
+        j = meta[:, 1] >> 16
+        local = j[:, None] * C + np.arange(C)[None, :]
         size = (part_start[part + 1] - part_start[part])[:, None]
         rows = np.where(local < size, part_start[part][:, None] + local, -1)
     else:
+        steps = meta[:, 1]
         er_row = np.asarray(view["er_row"], dtype=np.int64).reshape(ns, C)
         rows = np.where(er_row != 0xFFFF, part_start[part][:, None] + er_row, -1)
-    return meta[:, 0], meta[:, 1], part, rows
+    return meta[:, 0], steps, part, rows
 
 
 def _slots(view, which: str):
@@ -109,6 +118,22 @@ def _slots(view, which: str):
     return slot, row, k, valid, part_of_slice[s_of]
 
 
+def _ell_global(view, local, part):
+    """Permuted global column of ELL local columns: below the partition size
+    an x-slice element, otherwise a halo element."""
+    part_start = np.asarray(view["part_start"], dtype=np.int64)
+    halo_start = np.asarray(view["halo_start"], dtype=np.int64)
+    halo_idx = np.asarray(view["halo_idx"], dtype=np.int64)
+    size = part_start[part + 1] - part_start[part]
+    own = local < size
+    out = np.empty_like(local)
+    out[own] = part_start[part[own]] + local[own]
+    k = halo_start[part[~own]] + local[~own] - size[~own]
+    _req((k < halo_start[part[~own] + 1]).all(), "ELL column past the end of its halo")
+    out[~own] = halo_idx[k]
+    return out
+
+
 def layout_entries(view):
     """(row, col, val, in_ell) of every real stored entry, in permuted indices."""
     part_start = np.asarray(view["part_start"], dtype=np.int64)
@@ -120,7 +145,7 @@ def layout_entries(view):
         sv = slot[valid]
         col = cols[sv].astype(np.int64)
         if which == "ell":
-            col = col + part_start[part[valid]]
+            col = _ell_global(view, col, part[valid])
         out.append((row[valid], col, vals[sv], np.full(sv.size, which == "ell")))
     return tuple(np.concatenate([o[i] for o in out]) for i in range(4))
 
@@ -133,7 +158,7 @@ def layout_spmv(view, xp: np.ndarray) -> np.ndarray:
     return np.bincount(row, weights=val.astype(np.float64) * xp[col], minlength=n)
 
 
-def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap: int = 0,
+def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_cap: int = 0,
                value_dtype=np.float64, Bperm=None) -> dict:
     """Check every structural property of an EHYB encoding of ``A``.
 
@@ -154,13 +179,44 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
     sizes = np.diff(part_start)
     _req(n == 0 or (sizes > 0).all(), "empty partition")
     _req((sizes <= 65536).all(), "partition larger than a 16-bit local index allows")
-    _req((sizes * tau_x <= lds_budget).all(), "x-slice exceeds the on-chip budget")
+    # halo: ascending permuted indices outside the partition
+    halo_start = np.asarray(view["halo_start"], dtype=np.int64)
+    halo_idx = np.asarray(view["halo_idx"], dtype=np.int64)
+    _req(halo_start.shape == (nparts + 1,) and (nparts == 0 or halo_start[0] == 0)
+         and (nparts == 0 or halo_start[-1] == halo_idx.size) and (np.diff(halo_start) >= 0).all(),
+         "halo bounds")
+    hsz = np.diff(halo_start)
+    hpart = np.repeat(np.arange(nparts), hsz)
+    _req(((halo_idx >= 0) & (halo_idx < n)).all(), "halo index out of range")
+    _req(((halo_idx < part_start[hpart]) | (halo_idx >= part_start[hpart + 1])).all(),
+         "halo entry inside its own partition")
+    inner = hpart[1:] == hpart[:-1]
+    _req((np.diff(halo_idx)[inner] > 0).all(), "halo not strictly ascending")
+    _req((sizes + hsz <= 65535).all(), "LDS vector larger than a 16-bit local index allows")
+    has_er = int(np.asarray(view["er_meta"]).size) > 0
+    lds = (sizes.max(initial=0) + hsz.max(initial=0) + (sizes.max(initial=0) if has_er else 0)) * x_bytes
+    _req(lds <= lds_budget, "x-slice, halo and residual accumulators exceed the on-chip budget")
 
     L = int(view["L"])
     _req(L in (1, 2, 4, 8, 16, 32, 64), "lanes per row must divide 64")
     C = 64 // L
     slice_start = np.asarray(view["slice_start"], dtype=np.int64)
     _req(np.array_equal(np.diff(slice_start), -(-sizes // C)), "ELL slices per partition")
+    # ELL slices in queue order: the slices without residual rows (ascending),
+    # then the others (ascending); ell_free counts the first group
+    ell_meta = np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)
+    ell_free = np.asarray(view["ell_free"], dtype=np.int64)
+    _req(ell_free.shape == (nparts,), "ell_free length")
+    jj = ell_meta[:, 1] >> 16
+    dep = (ell_meta[:, 2] | ell_meta[:, 3]) != 0
+    for p in range(nparts):
+        a, b = slice_start[p], slice_start[p + 1]
+        _req(np.array_equal(np.sort(jj[a:b]), np.arange(b - a)), "ELL slice indices are not a permutation")
+        f = int(ell_free[p])
+        _req(0 <= f <= b - a and not dep[a:a + f].any() and dep[a + f:b].all(),
+             "ELL slices not in queue order (free slices first)")
+        _req((np.diff(jj[a:a + f]) > 0).all() and (np.diff(jj[a + f:b]) > 0).all(),
+             "ELL slices within a queue group are not ascending")
 
     kc = int(view["kc"])
     ell_val = np.asarray(view["ell_val"])
@@ -219,10 +275,11 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
         _req(not bits.any(), f"{which} padding slot is not +0.0")
         pc = cols[pad].astype(np.int64)
         if which == "ell":
-            _req((pc < sizes[part[~valid]]).all(), "ELL padding column outside its slice")
+            ext = sizes + hsz
+            _req((pc < ext[part[~valid]]).all(), "ELL padding column outside its LDS vector")
             rv = row[valid]
-            _req((cols[slot[valid]].astype(np.int64) < sizes[part_of_row[rv]]).all(),
-                 "ELL local column outside its partition")
+            _req((cols[slot[valid]].astype(np.int64) < ext[part_of_row[rv]]).all(),
+                 "ELL local column outside its LDS vector")
         else:
             _req(((pc >= 0) & (pc < n)).all(), "residual padding column out of range")
             _req((part_of_row[row[valid]] == part[valid]).all(),
@@ -230,13 +287,23 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
 
     row, col, val, in_ell = layout_entries(view)
     _req(((col >= 0) & (col < n)).all(), "column out of range")
-    same = part_of_row[row] == part_of_row[col]
-    _req(same[in_ell].all(), "ELL entry whose column is outside the row's partition")
+    rp = part_of_row[row]
+    same = rp == part_of_row[col]
+    # column cached in the row's halo?
+    if halo_idx.size:
+        key_h = hpart.astype(np.int64) * (n + 1) + halo_idx
+        key_e = rp.astype(np.int64) * (n + 1) + col
+        pos = np.clip(np.searchsorted(key_h, key_e), 0, key_h.size - 1)
+        cached = key_h[pos] == key_e
+    else:
+        cached = np.zeros(row.size, dtype=bool)
+    served = same | cached
+    _req(served[in_ell].all(), "ELL entry whose column is neither in the partition nor in its halo")
     if width_cap == 0:
-        _req((~same[~in_ell]).all(), "intra-partition entry left in the residual part")
+        _req((~served[~in_ell]).all(), "intra-partition entry left in the residual part")
     else:
         _req((row_ell_len <= width_cap).all(), "ELL row longer than the width cap")
-        spill = ~in_ell & same
+        spill = ~in_ell & served
         _req((row_ell_len[row[spill]] == width_cap).all(),
              "intra-partition entry spilled from a row below the cap")
 
@@ -265,7 +332,8 @@ def check_plan(A, view, tau_x: int = 8, lds_budget: int = 160 * 1024, width_cap:
     nnz_er = int((~in_ell).sum())
     return {
         "nnz": int(B.nnz), "nnz_ell": int(in_ell.sum()), "nnz_er": nnz_er,
-        "ell_slots": int(np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)[:, 1].sum() * 64 * kc),
+        "nnz_halo": int((in_ell & ~same).sum()), "n_halo": int(halo_idx.size),
+        "ell_slots": int((np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)[:, 1] & 0xFFFF).sum() * 64 * kc),
         "er_slots": int(np.asarray(view["er_meta"], dtype=np.int64).reshape(-1, 2)[:, 1].sum() * 64),
         "er_fraction": nnz_er / max(1, B.nnz), "nparts": nparts,
     }

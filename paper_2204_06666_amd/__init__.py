@@ -58,7 +58,7 @@ class Plan:
     def __init__(self, A=None, *, slice_rows: int = 0, ell_width_cap: int = 0,
                  rows_per_wave: int = 0, value_dtype: int = EHYB_F64, lds_bytes: int = 0,
                  num_cus: int = 0, n_threads: int = 0, imbalance_pct: int = 0,
-                 partitioner: int = 0, seed: int = 0, _handle=None):
+                 partitioner: int = 0, halo_rows: int = 0, seed: int = 0, _handle=None):
         self._lib = load()
         self._h = ctypes.c_void_p()
         self._blob = None
@@ -71,7 +71,7 @@ class Plan:
                            rp.ctypes.data, ci.ctypes.data if ci.size else None,
                            v.ctypes.data if v.size else None)
         prm = _abi.Params(slice_rows, ell_width_cap, rows_per_wave, value_dtype, lds_bytes,
-                          num_cus, n_threads, imbalance_pct, partitioner, 0, seed)
+                          num_cus, n_threads, imbalance_pct, partitioner, halo_rows, seed)
         check(self._lib.ehyb_preprocess(ctypes.byref(csr), ctypes.byref(prm), ctypes.byref(self._h)),
               "ehyb_preprocess")
         self.n = int(A.n_rows)
@@ -90,7 +90,7 @@ class Plan:
     def stats(self) -> dict:
         st = _abi.PlanStats()
         check(self._lib.ehyb_plan_stats_get(self._h, ctypes.byref(st)), "ehyb_plan_stats_get")
-        return {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}
+        return {f: getattr(st, f) for f, _ in st._fields_}
 
     def arrays(self) -> dict:
         """Copies of the plan's host arrays (the layout of include/ehyb.h)."""
@@ -112,6 +112,9 @@ class Plan:
             perm=grab(ar.perm, n, np.int32), part_start=grab(ar.part_start, nparts + 1, np.int32),
             slice_start=grab(ar.slice_start, nparts + 1, np.int32),
             er_slice_start=grab(ar.er_slice_start, nparts + 1, np.int32),
+            ell_free=grab(ar.ell_free, nparts, np.int32),
+            halo_start=grab(ar.halo_start, nparts + 1, np.int32),
+            halo_idx=grab(ar.halo_idx, ar.n_halo, np.int32),
             ell_meta=grab(ar.ell_meta, 4 * ns, np.uint32).reshape(ns, 4),
             er_meta=grab(ar.er_meta, 2 * nes, np.uint32).reshape(nes, 2),
             er_row=grab(ar.er_row, C * nes, np.uint16).reshape(nes, C),

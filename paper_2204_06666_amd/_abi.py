@@ -26,16 +26,18 @@ class Params(ctypes.Structure):
     _fields_ = [("slice_rows", c_i32), ("ell_width_cap", c_i32), ("rows_per_wave", c_i32),
                 ("value_dtype", c_i32), ("lds_bytes", c_i32), ("num_cus", c_i32),
                 ("n_threads", c_i32), ("imbalance_pct", c_i32), ("partitioner", c_i32),
-                ("reserved", c_i32), ("seed", c_u64)]
+                ("halo_rows", c_i32), ("seed", c_u64)]
 
 
 class PlanStats(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nnz", c_i64), ("nnz_ell", c_i64), ("nnz_er", c_i64),
                 ("ell_slots", c_i64), ("er_slots", c_i64), ("n_er_rows", c_i64),
+                ("nnz_halo", c_i64), ("n_halo", c_i64),
                 ("device_bytes", c_i64), ("algorithmic_bytes", c_i64),
                 ("nparts", c_i32), ("nslices", c_i32), ("ner_slices", c_i32), ("slice_rows", c_i32),
                 ("max_part_rows", c_i32), ("rows_per_slice", c_i32), ("lanes_per_row", c_i32),
                 ("kc", c_i32), ("value_dtype", c_i32), ("eq1_K", c_i32),
+                ("max_halo", c_i32), ("lds_bytes_used", c_i32),
                 ("t_graph_s", ctypes.c_double), ("t_partition_s", ctypes.c_double),
                 ("t_reorder_s", ctypes.c_double), ("t_encode_s", ctypes.c_double)]
 
@@ -43,8 +45,9 @@ class PlanStats(ctypes.Structure):
 class PlanArrays(ctypes.Structure):
     _fields_ = [("n", c_i64), ("nparts", c_i32), ("nslices", c_i32), ("ner_slices", c_i32),
                 ("lanes_per_row", c_i32), ("kc", c_i32), ("value_dtype", c_i32),
-                ("ell_slots", c_i64), ("er_slots", c_i64),
+                ("ell_slots", c_i64), ("er_slots", c_i64), ("n_halo", c_i64),
                 ("perm", c_vp), ("part_start", c_vp), ("slice_start", c_vp), ("er_slice_start", c_vp),
+                ("ell_free", c_vp), ("halo_start", c_vp), ("halo_idx", c_vp),
                 ("ell_meta", c_vp), ("er_meta", c_vp), ("er_row", c_vp),
                 ("ell_val", c_vp), ("ell_col", c_vp), ("er_val", c_vp), ("er_col", c_vp),
                 ("row_ell_len", c_vp), ("row_er_len", c_vp)]

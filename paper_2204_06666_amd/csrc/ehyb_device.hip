@@ -27,7 +27,10 @@ struct SpmvF64Args {
     const int32_t* part_start;      // [nparts+1] first permuted row of each partition
     const int32_t* slice_start;     // [nparts+1] first ELL row-slice of each partition
     const int32_t* er_slice_start;  // [nparts+1] first residual row-slice of each partition
-    const uint4* ell_meta;          // slot offset, steps, residual-row mask (lo, hi)
+    const int32_t* ell_free;        // [nparts] leading ELL slices without residual rows
+    const int32_t* halo_start;      // [nparts+1]
+    const int32_t* halo_idx;        // cached neighbour x entries (permuted indices)
+    const uint4* ell_meta;          // slot offset, steps | index << 16, residual-row mask (lo, hi)
     const uint2* er_meta;           // slot offset, steps
     const uint16_t* er_row;         // local row of each residual slice row, 0xFFFF = none
     const double* ell_val;
@@ -36,12 +39,13 @@ struct SpmvF64Args {
     const int32_t* er_col;
     const double* x;                // permuted order
     double* y;                      // permuted order
-    int32_t lds_rows;               // rows reserved in each LDS array
+    int32_t lds_rows;               // LDS elements before the residual accumulators
 };
 
 constexpr int kEllChunk = 16;   // ELL steps whose loads are issued before any is used
-constexpr int kErChunk = 8;     // residual steps likewise
+constexpr int kErChunk = 16;    // residual steps likewise
 constexpr int kStageRegs = 4;   // 16-byte x-slice loads per thread kept in flight
+constexpr int kHaloRegs = 2;    // halo gathers per thread kept in flight
 
 template <int L>
 __device__ __forceinline__ double reduce_lanes(double v) {
@@ -52,24 +56,61 @@ __device__ __forceinline__ double reduce_lanes(double v) {
     return v;
 }
 
-// One workgroup per partition (Alg. 3).  Phases:
-//  1. issue the loads of the partition's x-slice (held in registers);
-//  2. residual part: wavefronts take the partition's residual row-slices in
-//     turn, gather x from device memory and leave each row's sum in an LDS
-//     accumulator (each residual row is owned by one lane group, so a plain
-//     store suffices);
-//  3. write the x-slice to LDS; barrier;
-//  4. ELL part: wavefronts take row-slices from a workgroup counter (the
-//     balancing of Alg. 3), issue every load of a slice (up to kEllChunk steps
-//     of a 16-byte value pair and a 4-byte column pair per lane) before
-//     consuming any, multiply-add against the LDS x-slice, add the residual
-//     sum of rows that have one, and store y once.
-// The sum of a row is (ELL entries in column order) + (residual entries in
-// column order), fixed by the plan: results are bitwise reproducible.
+// Metadata is the same for the whole wavefront: keep it in scalar registers.
+__device__ __forceinline__ uint4 uniform4(uint4 v) {
+    return make_uint4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
+                      __builtin_amdgcn_readfirstlane(v.z), __builtin_amdgcn_readfirstlane(v.w));
+}
+
+__device__ __forceinline__ int wave_fetch_add(int* ctr, int lane) {
+    int v = 0;
+    if (lane == 0) v = atomicAdd(ctr, 1);
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Release this wave's LDS writes, then count it in `ctr`.
+__device__ __forceinline__ void wave_signal(int* ctr, int lane) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) atomicAdd(ctr, 1);
+}
+
+// Wait (sleeping) until `ctr` reaches `target`, then acquire the LDS writes
+// released before each increment.  Every increment is made by a wavefront of
+// this workgroup that waits on nothing before making it, so the wait ends.
+__device__ __forceinline__ void wave_wait(int* ctr, int target) {
+    while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(ctr, __ATOMIC_RELAXED,
+                                                            __HIP_MEMORY_SCOPE_WORKGROUP)) < target)
+        __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// One workgroup per partition (Alg. 3); its wavefronts pull work from two
+// workgroup queues (the balancing of Alg. 3):
+//  1. the workgroup loads the partition's x-slice into LDS (the cached vector
+//     of Alg. 3) followed by its halo, the x entries of other partitions that
+//     the partition's ELL entries reference;
+//  2. residual queue: a wavefront takes a residual row-slice, loads all its
+//     columns and values (up to kErChunk steps at once), gathers x from
+//     device memory for all of them, and leaves each row's sum in an LDS
+//     accumulator (each residual row belongs to one lane group: plain
+//     store), then counts the slice.  The next slice's metadata is fetched
+//     while the current one is processed;
+//  3. ELL queue (slices without residual rows first): a wavefront takes a
+//     row-slice, issues all its loads (up to kEllChunk steps of a 16-byte
+//     value pair and a 4-byte column pair per lane) before using any,
+//     multiply-adds against the LDS vector (x-slice and halo) and stores y
+//     once.  A slice with
+//     residual rows first waits until the residual queue is drained, then
+//     adds the residual sums.
+// Wavefronts that leave the residual queue early stream ELL slices while
+// others still gather, so the latency-bound residual work overlaps the
+// streaming.  The sum of a row is (ELL entries in column order) + (residual
+// entries in column order), fixed by the plan: results are bitwise
+// reproducible.
 template <int L>
 __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
     extern __shared__ double lds[];
-    __shared__ int ell_next;
+    __shared__ int q_er, q_ell, n_staged, n_er_done;
     double* xs = lds;
     double* yer = lds + a.lds_rows;
     constexpr int C = kWave / L;
@@ -78,104 +119,146 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
     const int sz = a.part_start[p + 1] - ps;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int lane = tid & (kWave - 1);
-    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int nwaves = nthr >> 6;
     const int r = lane / L;
-    if (tid == 0) ell_next = 0;
-
-    // 1. x-slice loads: 16-byte loads over the aligned body
-    const double* src = a.x + ps;
-    const int head = (int)(((uintptr_t)src >> 3) & 1);  // 1 if src is 8- but not 16-byte aligned
-    const int h = head < sz ? head : sz;
-    const int nvec = (sz - h) >> 1;
-    const double2* src2 = reinterpret_cast<const double2*>(src + h);
-    double2 stg[kStageRegs];
-#pragma unroll
-    for (int j = 0; j < kStageRegs; ++j) {
-        const int i = tid + j * nthr;
-        if (i < nvec) stg[j] = src2[i];
+    if (tid == 0) {
+        q_er = 0;
+        q_ell = 0;
+        n_staged = 0;
+        n_er_done = 0;
     }
 
-    // 2. residual part
-    const int e0 = a.er_slice_start[p], e1 = a.er_slice_start[p + 1];
-    for (int e = e0 + wave; e < e1; e += nwaves) {
-        const uint2 m = a.er_meta[e];
-        const double* ev = a.er_val + m.x + lane;
-        const int32_t* ec = a.er_col + m.x + lane;
-        double acc = 0.0;
-        for (uint32_t t0 = 0; t0 < m.y; t0 += kErChunk) {
-            int32_t c[kErChunk];
-            double v[kErChunk], xg[kErChunk];
+    // 1. x-slice into LDS (16-byte loads over the aligned body)
+    {
+        const double* src = a.x + ps;
+        const int head = (int)(((uintptr_t)src >> 3) & 1);  // 1 if src is 8- but not 16-byte aligned
+        const int h = head < sz ? head : sz;
+        const int nvec = (sz - h) >> 1;
+        const double2* src2 = reinterpret_cast<const double2*>(src + h);
+        double2 stg[kStageRegs];
 #pragma unroll
-            for (int j = 0; j < kErChunk; ++j)
-                if (t0 + j < m.y) {
-                    c[j] = ec[(size_t)(t0 + j) * kWave];
-                    v[j] = ev[(size_t)(t0 + j) * kWave];
-                }
-#pragma unroll
-            for (int j = 0; j < kErChunk; ++j)
-                if (t0 + j < m.y) xg[j] = a.x[c[j]];
-#pragma unroll
-            for (int j = 0; j < kErChunk; ++j)
-                if (t0 + j < m.y) acc = fma(v[j], xg[j], acc);
+        for (int j = 0; j < kStageRegs; ++j) {
+            const int i = tid + j * nthr;
+            if (i < nvec) stg[j] = src2[i];
         }
-        acc = reduce_lanes<L>(acc);
-        const uint16_t lr = a.er_row[(size_t)e * C + r];
-        if ((lane & (L - 1)) == 0 && lr != 0xFFFF) yer[lr] = acc;
-    }
-
-    // 3. x-slice into LDS
 #pragma unroll
-    for (int j = 0; j < kStageRegs; ++j) {
-        const int i = tid + j * nthr;
-        if (i < nvec) {
-            xs[h + 2 * i] = stg[j].x;
-            xs[h + 2 * i + 1] = stg[j].y;
+        for (int j = 0; j < kStageRegs; ++j) {
+            const int i = tid + j * nthr;
+            if (i < nvec) {
+                xs[h + 2 * i] = stg[j].x;
+                xs[h + 2 * i + 1] = stg[j].y;
+            }
+        }
+        for (int i = tid + kStageRegs * nthr; i < nvec; i += nthr) {
+            const double2 v = src2[i];
+            xs[h + 2 * i] = v.x;
+            xs[h + 2 * i + 1] = v.y;
+        }
+        if (tid < h) xs[0] = src[0];
+        const int tail = h + 2 * nvec;
+        if (tid < sz - tail) xs[tail + tid] = src[tail + tid];
+        // halo after the x-slice: index loads, then gathers
+        const int hs = a.halo_start[p];
+        const int hn = a.halo_start[p + 1] - hs;
+        int hi[kHaloRegs];
+#pragma unroll
+        for (int j = 0; j < kHaloRegs; ++j) {
+            const int i = tid + j * nthr;
+            if (i < hn) hi[j] = a.halo_idx[hs + i];
+        }
+        double hv[kHaloRegs];
+#pragma unroll
+        for (int j = 0; j < kHaloRegs; ++j) {
+            const int i = tid + j * nthr;
+            if (i < hn) hv[j] = a.x[hi[j]];
+        }
+#pragma unroll
+        for (int j = 0; j < kHaloRegs; ++j) {
+            const int i = tid + j * nthr;
+            if (i < hn) xs[sz + i] = hv[j];
+        }
+        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr) xs[sz + i] = a.x[a.halo_idx[hs + i]];
+    }
+    __syncthreads();  // counters initialised, x-slice and halo in LDS
+
+    // 2. residual queue
+    const int e0 = a.er_slice_start[p];
+    const int ner = a.er_slice_start[p + 1] - e0;
+    {
+        int it = wave_fetch_add(&q_er, lane);
+        uint2 m = it < ner ? a.er_meta[e0 + it] : make_uint2(0, 0);
+        while (it < ner) {
+            const int itn = wave_fetch_add(&q_er, lane);
+            const uint2 mn = itn < ner ? a.er_meta[e0 + itn] : make_uint2(0, 0);
+            const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
+            const uint32_t steps = __builtin_amdgcn_readfirstlane(m.y);
+            const double* ev = a.er_val + off + lane;
+            const int32_t* ec = a.er_col + off + lane;
+            const uint16_t lr = a.er_row[(size_t)(e0 + it) * C + r];
+            double acc = 0.0;
+            for (uint32_t t0 = 0; t0 < steps; t0 += kErChunk) {
+                int32_t c[kErChunk];
+                double v[kErChunk], xg[kErChunk];
+#pragma unroll
+                for (int j = 0; j < kErChunk; ++j)
+                    if (t0 + j < steps) {
+                        c[j] = ec[(size_t)(t0 + j) * kWave];
+                        v[j] = ev[(size_t)(t0 + j) * kWave];
+                    }
+#pragma unroll
+                for (int j = 0; j < kErChunk; ++j)
+                    if (t0 + j < steps) xg[j] = a.x[c[j]];
+#pragma unroll
+                for (int j = 0; j < kErChunk; ++j)
+                    if (t0 + j < steps) acc = fma(v[j], xg[j], acc);
+            }
+            acc = reduce_lanes<L>(acc);
+            if ((lane & (L - 1)) == 0 && lr != 0xFFFF) yer[lr] = acc;
+            wave_signal(&n_er_done, lane);
+            it = itn;
+            m = mn;
         }
     }
-    for (int i = tid + kStageRegs * nthr; i < nvec; i += nthr) {
-        const double2 v = src2[i];
-        xs[h + 2 * i] = v.x;
-        xs[h + 2 * i + 1] = v.y;
-    }
-    if (tid < h) xs[0] = src[0];
-    const int tail = h + 2 * nvec;
-    if (tid < sz - tail) xs[tail + tid] = src[tail + tid];
-    __syncthreads();
 
-    // 4. ELL part
+    // 3. ELL queue
     const int s0 = a.slice_start[p];
     const int ns = a.slice_start[p + 1] - s0;
-    int item = wave;
+    bool er_ready = ner == 0;
+    int item = wave_fetch_add(&q_ell, lane);
     uint4 m = item < ns ? a.ell_meta[s0 + item] : make_uint4(0, 0, 0, 0);
     while (item < ns) {
-        int nxt = 0;
-        if (lane == 0) nxt = atomicAdd(&ell_next, 1);
-        nxt = __builtin_amdgcn_readfirstlane(nxt) + nwaves;
+        const int nxt = wave_fetch_add(&q_ell, lane);
         // the next slice's metadata travels while this slice streams
         const uint4 mn = nxt < ns ? a.ell_meta[s0 + nxt] : make_uint4(0, 0, 0, 0);
-        const double2* v2 = reinterpret_cast<const double2*>(a.ell_val + m.x) + lane;
-        const uint32_t* c2 = reinterpret_cast<const uint32_t*>(a.ell_col + m.x) + lane;
+        const uint4 mu = uniform4(m);
+        const uint32_t steps = mu.y & 0xFFFFu;
+        const int j0 = (int)(mu.y >> 16);
+        const double2* v2 = reinterpret_cast<const double2*>(a.ell_val + mu.x) + lane;
+        const uint32_t* c2 = reinterpret_cast<const uint32_t*>(a.ell_col + mu.x) + lane;
         double acc = 0.0;
-        for (uint32_t t0 = 0; t0 < m.y; t0 += kEllChunk) {
+        for (uint32_t t0 = 0; t0 < steps; t0 += kEllChunk) {
             double2 v[kEllChunk];
             uint32_t c[kEllChunk];
 #pragma unroll
             for (int j = 0; j < kEllChunk; ++j)
-                if (t0 + j < m.y) {
+                if (t0 + j < steps) {
                     v[j] = v2[(size_t)(t0 + j) * kWave];
                     c[j] = c2[(size_t)(t0 + j) * kWave];
                 }
 #pragma unroll
             for (int j = 0; j < kEllChunk; ++j)
-                if (t0 + j < m.y) {
+                if (t0 + j < steps) {
                     acc = fma(v[j].x, xs[c[j] & 0xFFFFu], acc);
                     acc = fma(v[j].y, xs[c[j] >> 16], acc);
                 }
         }
         acc = reduce_lanes<L>(acc);
-        const int lr = item * C + r;
-        const uint64_t mask = ((uint64_t)m.w << 32) | m.z;
+        const uint64_t mask = ((uint64_t)mu.w << 32) | mu.z;
+        if (mask != 0 && !er_ready) {
+            wave_wait(&n_er_done, ner);
+            er_ready = true;
+        }
+        const int lr = j0 * C + r;
         if ((lane & (L - 1)) == 0 && lr < sz) {
             if ((mask >> r) & 1u) acc += yer[lr];
             a.y[ps + lr] = acc;
@@ -274,7 +357,7 @@ void launch_spmv_f64(const SpmvF64Args& a, int nblocks, int threads, size_t lds,
     if (!lds_raised && lds > 64 * 1024) {
         // allow the full 160 KiB of gfx950 LDS as dynamic shared memory
         if (hipFuncSetAttribute(reinterpret_cast<const void*>(&ehyb_spmv_f64_kernel<L>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - 64) != hipSuccess)
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - kStaticLds) != hipSuccess)
             (void)hipGetLastError();
         lds_raised = true;
     }
@@ -302,6 +385,9 @@ ehyb_status ehyb_plan_upload(ehyb_plan* P, void* dev_blob, size_t bytes, void* s
         {L.part_start, P->part_start.data(), P->part_start.size() * 4},
         {L.slice_start, P->slice_start.data(), P->slice_start.size() * 4},
         {L.er_slice_start, P->er_slice_start.data(), P->er_slice_start.size() * 4},
+        {L.ell_free, P->ell_free.data(), P->ell_free.size() * 4},
+        {L.halo_start, P->halo_start.data(), P->halo_start.size() * 4},
+        {L.halo_idx, P->halo_idx.data(), P->halo_idx.size() * 4},
         {L.ell_meta, P->ell_meta.data(), P->ell_meta.size() * 4},
         {L.er_meta, P->er_meta.data(), P->er_meta.size() * 4},
         {L.er_row, P->er_row.data(), P->er_row.size() * 2},
@@ -388,6 +474,9 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     a.part_start = (const int32_t*)(blob + Ly.part_start);
     a.slice_start = (const int32_t*)(blob + Ly.slice_start);
     a.er_slice_start = (const int32_t*)(blob + Ly.er_slice_start);
+    a.ell_free = (const int32_t*)(blob + Ly.ell_free);
+    a.halo_start = (const int32_t*)(blob + Ly.halo_start);
+    a.halo_idx = (const int32_t*)(blob + Ly.halo_idx);
     a.ell_meta = (const uint4*)(blob + Ly.ell_meta);
     a.er_meta = (const uint2*)(blob + Ly.er_meta);
     a.er_row = (const uint16_t*)(blob + Ly.er_row);
@@ -397,10 +486,10 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     a.er_col = (const int32_t*)(blob + Ly.er_col);
     a.x = xin;
     a.y = yout;
-    a.lds_rows = P->max_part_rows;
+    a.lds_rows = P->max_part_rows + P->max_halo;
     const int nblocks = P->nparts;
-    const size_t lds = (size_t)P->max_part_rows * 16;
-    if (lds > 160 * 1024 - 64) return fail(EHYB_EUNSUPPORTED, "partition larger than the LDS budget");
+    const size_t lds = (size_t)lds_bytes_used(*P);
+    if (lds > 160 * 1024 - kStaticLds) return fail(EHYB_EUNSUPPORTED, "partition and halo larger than the LDS budget");
     const int threads = launch_waves(*P) * kWave;
     switch (P->L) {
         case 1: launch_spmv_f64<1>(a, nblocks, threads, lds, s); break;

@@ -214,7 +214,8 @@ int64_t algorithmic_bytes(const ehyb_plan& p) {
     b += p.er_slots * (p.vbytes + 4);                  // residual values + 32-bit columns
     b += (int64_t)p.nslices * 16;                      // ELL slice metadata
     b += (int64_t)p.ner_slices * (8 + 2 * p.C);        // residual slice metadata + row indices
-    b += (int64_t)(p.nparts + 1) * 12;                 // partition and slice bounds
+    b += (int64_t)(p.nparts + 1) * 16 + (int64_t)p.nparts * 4;  // partition, slice and halo bounds
+    b += (int64_t)p.halo_idx.size() * 4;                         // halo indices
     b += p.n * p.xbytes;                               // x, each element once (slice staging)
     b += p.n * p.xbytes;                               // y, written once
     return b;
@@ -231,6 +232,9 @@ BlobLayout compute_layout(const ehyb_plan& p) {
     L.part_start = take((size_t)(p.nparts + 1) * 4);
     L.slice_start = take((size_t)(p.nparts + 1) * 4);
     L.er_slice_start = take((size_t)(p.nparts + 1) * 4);
+    L.ell_free = take((size_t)p.nparts * 4);
+    L.halo_start = take((size_t)(p.nparts + 1) * 4);
+    L.halo_idx = take(p.halo_idx.size() * 4);
     L.ell_meta = take((size_t)p.nslices * 16);
     L.er_meta = take((size_t)p.ner_slices * 8);
     L.er_row = take((size_t)p.ner_slices * p.C * 2);
@@ -243,6 +247,13 @@ BlobLayout compute_layout(const ehyb_plan& p) {
     L.yp = take((size_t)p.n * p.xbytes);
     L.total = off == 0 ? kBlobAlign : off;
     return L;
+}
+
+// LDS of one ehyb_spmv workgroup: x-slice + halo, then one residual
+// accumulator per row when the plan has residual entries.
+int64_t lds_bytes_used(const ehyb_plan& p) {
+    const int64_t rows = (int64_t)p.max_part_rows + p.max_halo + (p.ner_slices > 0 ? p.max_part_rows : 0);
+    return rows * p.xbytes;
 }
 
 // Residual position of every permuted row (e*C + r, or -1), from er_row.
@@ -275,25 +286,13 @@ inline int64_t er_slot_of(int64_t off, int32_t k, int32_t r, int L) {
 // Alg. 1 (classification and reordering) and Alg. 2 (moving entries into the
 // ELL and residual parts), given the partition vector.
 ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part, int32_t nparts,
-                       ehyb_plan* P) {
+                       int32_t halo_cap, ehyb_plan* P) {
     const int32_t n = (int32_t)A->n_rows;
     const int cap = P->params.ell_width_cap;
     const int L = P->L, C = P->C, kc = P->kc;
     double t0 = now_s();
 
-    // Alg. 1: in-partition (ELL) and other (residual) entry counts per row
-    std::vector<int32_t> ell_cnt(n), er_cnt(n);
-#pragma omp parallel for schedule(static)
-    for (int32_t i = 0; i < n; ++i) {
-        int32_t in = 0;
-        for (int64_t p = A->row_ptr[i]; p < A->row_ptr[i + 1]; ++p)
-            if (part[A->col_idx[p]] == part[i]) ++in;
-        const int32_t len = (int32_t)(A->row_ptr[i + 1] - A->row_ptr[i]);
-        ell_cnt[i] = (cap > 0 && in > cap) ? cap : in;
-        er_cnt[i] = len - ell_cnt[i];
-    }
-    // rows grouped by partition (stable in the original index), then each
-    // partition sorted by non-increasing ELL count (stable)
+    // rows of each partition, in original order
     P->part_start.assign(nparts + 1, 0);
     for (int32_t i = 0; i < n; ++i) P->part_start[part[i] + 1]++;
     for (int32_t p = 0; p < nparts; ++p) P->part_start[p + 1] += P->part_start[p];
@@ -302,12 +301,80 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
         std::vector<int32_t> fill(P->part_start.begin(), P->part_start.end() - 1);
         for (int32_t i = 0; i < n; ++i) P->perm[fill[part[i]]++] = i;
     }
+
+    // Halo of each partition: the out-of-partition columns its rows reference,
+    // most referenced first, at most halo_cap of them (original indices here).
+    std::vector<std::vector<int32_t>> halo(nparts);
+    std::vector<int32_t> ell_cnt(n), er_cnt(n);
+#pragma omp parallel
+    {
+        std::vector<int32_t> ext;
+        std::vector<std::pair<int32_t, int32_t>> cnt;   // (-count, column)
+        std::vector<char> in_halo(halo_cap > 0 ? n : 0, 0);
+#pragma omp for schedule(dynamic, 1)
+        for (int32_t p = 0; p < nparts; ++p) {
+            auto& h = halo[p];
+            if (halo_cap > 0) {
+                ext.clear();
+                for (int32_t k = P->part_start[p]; k < P->part_start[p + 1]; ++k) {
+                    const int32_t i = P->perm[k];
+                    for (int64_t q = A->row_ptr[i]; q < A->row_ptr[i + 1]; ++q)
+                        if (part[A->col_idx[q]] != p) ext.push_back(A->col_idx[q]);
+                }
+                std::sort(ext.begin(), ext.end());
+                cnt.clear();
+                for (size_t a = 0; a < ext.size();) {
+                    size_t b = a;
+                    while (b < ext.size() && ext[b] == ext[a]) ++b;
+                    cnt.emplace_back(-(int32_t)(b - a), ext[a]);
+                    a = b;
+                }
+                if ((int64_t)cnt.size() > halo_cap) {
+                    std::sort(cnt.begin(), cnt.end());
+                    cnt.resize(halo_cap);
+                }
+                h.reserve(cnt.size());
+                for (const auto& c : cnt) h.push_back(c.second);
+                for (int32_t j : h) in_halo[j] = 1;
+            }
+            // Alg. 1: entries served by the partition's LDS vector (own x-slice
+            // or halo) go to the ELL part, the others to the residual part
+            for (int32_t k = P->part_start[p]; k < P->part_start[p + 1]; ++k) {
+                const int32_t i = P->perm[k];
+                int32_t in = 0;
+                for (int64_t q = A->row_ptr[i]; q < A->row_ptr[i + 1]; ++q) {
+                    const int32_t j = A->col_idx[q];
+                    if (part[j] == p || (halo_cap > 0 && in_halo[j])) ++in;
+                }
+                const int32_t len = (int32_t)(A->row_ptr[i + 1] - A->row_ptr[i]);
+                ell_cnt[i] = (cap > 0 && in > cap) ? cap : in;
+                er_cnt[i] = len - ell_cnt[i];
+            }
+            if (halo_cap > 0)
+                for (int32_t j : h) in_halo[j] = 0;
+        }
+    }
+    // each partition's rows by non-increasing ELL count (stable in the
+    // original index)
 #pragma omp parallel for schedule(dynamic, 1)
     for (int32_t p = 0; p < nparts; ++p)
         std::stable_sort(P->perm.begin() + P->part_start[p], P->perm.begin() + P->part_start[p + 1],
                          [&](int32_t a, int32_t b) { return ell_cnt[a] > ell_cnt[b]; });
     P->iperm.resize(n);
     for (int32_t i = 0; i < n; ++i) P->iperm[P->perm[i]] = i;
+    // halos in permuted indices, ascending
+    P->halo_start.assign(nparts + 1, 0);
+    int32_t maxh = 0;
+    for (int32_t p = 0; p < nparts; ++p) {
+        for (auto& j : halo[p]) j = P->iperm[j];
+        std::sort(halo[p].begin(), halo[p].end());
+        P->halo_start[p + 1] = P->halo_start[p] + (int32_t)halo[p].size();
+        maxh = std::max(maxh, (int32_t)halo[p].size());
+    }
+    P->max_halo = maxh;
+    P->halo_idx.resize(P->halo_start[nparts]);
+    for (int32_t p = 0; p < nparts; ++p)
+        std::copy(halo[p].begin(), halo[p].end(), P->halo_idx.begin() + P->halo_start[p]);
     P->row_ell_len.resize(n);
     P->row_er_len.resize(n);
     int32_t maxp = 0;
@@ -343,37 +410,59 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     P->t_reorder = now_s() - t0;
     t0 = now_s();
 
-    // ELL row-slices: C consecutive rows of one partition
+    // ELL row-slices: C consecutive rows of one partition, stored in the order
+    // a workgroup takes them: slices without residual rows first
     P->slice_start.assign(nparts + 1, 0);
     for (int32_t p = 0; p < nparts; ++p)
         P->slice_start[p + 1] = P->slice_start[p] + (P->part_start[p + 1] - P->part_start[p] + C - 1) / C;
     const int32_t ns = P->slice_start[nparts];
     P->nslices = ns;
-    std::vector<int32_t> slice_part(ns);
-    for (int32_t p = 0; p < nparts; ++p)
-        for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) slice_part[s] = p;
+    if (ns > 0 && (P->part_start[nparts] + C - 1) / C > 0) {
+        for (int32_t p = 0; p < nparts; ++p)
+            if (P->slice_start[p + 1] - P->slice_start[p] > 65535)
+                return fail(EHYB_EUNSUPPORTED, "more than 65535 row-slices in one partition");
+    }
+    std::vector<int32_t> slice_part(ns), slice_j(ns);
     std::vector<int64_t> ell_steps(ns);
     std::vector<uint64_t> er_mask(ns, 0);
-#pragma omp parallel for schedule(static)
-    for (int32_t s = 0; s < ns; ++s) {
-        const int32_t p = slice_part[s];
-        const int32_t r0 = P->part_start[p] + (s - P->slice_start[p]) * C;
-        const int32_t r1 = std::min(r0 + C, P->part_start[p + 1]);
-        int32_t me = 0;
-        uint64_t mask = 0;
-        for (int32_t r = r0; r < r1; ++r) {
-            me = std::max(me, P->row_ell_len[r]);
-            if (P->row_er_len[r] > 0) mask |= 1ull << (r - r0);
+    P->ell_free.assign(nparts, 0);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int32_t p = 0; p < nparts; ++p) {
+        const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
+        const int32_t nsp = P->slice_start[p + 1] - P->slice_start[p];
+        std::vector<uint64_t> mk(nsp);
+        std::vector<int64_t> st(nsp);
+        for (int32_t j = 0; j < nsp; ++j) {
+            const int32_t r0 = ps + j * C, r1 = std::min(r0 + C, pe);
+            int32_t me = 0;
+            uint64_t mask = 0;
+            for (int32_t r = r0; r < r1; ++r) {
+                me = std::max(me, P->row_ell_len[r]);
+                if (P->row_er_len[r] > 0) mask |= 1ull << (r - r0);
+            }
+            mk[j] = mask;
+            st[j] = (me + L * kc - 1) / (L * kc);
         }
-        ell_steps[s] = (me + L * kc - 1) / (L * kc);
-        er_mask[s] = mask;
+        int32_t at = P->slice_start[p], nfree = 0;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int32_t j = 0; j < nsp; ++j)
+                if ((mk[j] == 0) == (pass == 0)) {
+                    slice_part[at] = p;
+                    slice_j[at] = j;
+                    ell_steps[at] = st[j];
+                    er_mask[at] = mk[j];
+                    ++at;
+                    nfree += pass == 0;
+                }
+        P->ell_free[p] = nfree;
     }
     P->ell_meta.assign((size_t)ns * 4, 0);
     int64_t eoff = 0;
     for (int32_t s = 0; s < ns; ++s) {
         if (eoff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the ELL part");
+        if (ell_steps[s] > 65535) return fail(EHYB_EUNSUPPORTED, "ELL row-slice wider than 65535 steps");
         P->ell_meta[4 * (size_t)s + 0] = (uint32_t)eoff;
-        P->ell_meta[4 * (size_t)s + 1] = (uint32_t)ell_steps[s];
+        P->ell_meta[4 * (size_t)s + 1] = (uint32_t)ell_steps[s] | ((uint32_t)slice_j[s] << 16);
         P->ell_meta[4 * (size_t)s + 2] = (uint32_t)(er_mask[s] & 0xFFFFFFFFu);
         P->ell_meta[4 * (size_t)s + 3] = (uint32_t)(er_mask[s] >> 32);
         eoff += ell_steps[s] * kWave * kc;
@@ -414,15 +503,15 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
 
     // Alg. 2: move each entry, with its column renumbered by the reorder
     // table, into its slot
-    int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0;
-#pragma omp parallel reduction(+ : nnz_ell, nnz_er, n_er_rows)
+    int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0, nnz_halo = 0;
+#pragma omp parallel reduction(+ : nnz_ell, nnz_er, n_er_rows, nnz_halo)
     {
         std::vector<std::pair<int32_t, int64_t>> ent;  // (new column, source position)
 #pragma omp for schedule(dynamic, 64)
         for (int32_t s = 0; s < ns; ++s) {
             const int32_t p = slice_part[s];
             const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
-            const int32_t r0 = ps + (s - P->slice_start[p]) * C;
+            const int32_t r0 = ps + slice_j[s] * C;
             const int32_t r1 = std::min(r0 + C, pe);
             const int64_t eo = P->ell_meta[4 * (size_t)s + 0];
             for (int32_t row = r0; row < r1; ++row) {
@@ -437,13 +526,23 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                 const int32_t ep = P->er_pos[row];
                 const int64_t ro = ep >= 0 ? (int64_t)P->er_meta[2 * (size_t)(ep / C)] : 0;
                 const int32_t rr = ep >= 0 ? ep % C : 0;
+                const int32_t* hb = P->halo_idx.data() + P->halo_start[p];
+                const int32_t* he = P->halo_idx.data() + P->halo_start[p + 1];
                 for (const auto& pr : ent) {
                     const int32_t nc = pr.first;
                     const double v = A->val[pr.second];
-                    if (nc >= ps && nc < pe && k1 < ell_len) {
+                    int32_t local = -1;
+                    if (nc >= ps && nc < pe) {
+                        local = nc - ps;
+                    } else {
+                        const int32_t* f = std::lower_bound(hb, he, nc);
+                        if (f != he && *f == nc) local = (pe - ps) + (int32_t)(f - hb);
+                    }
+                    if (local >= 0 && k1 < ell_len) {
                         const int64_t slot = ell_slot_of(eo, k1++, r, L, kc);
                         store_value(&P->ell_val[(size_t)slot * vb], vb, dt, v);
-                        P->ell_col[slot] = (uint16_t)(nc - ps);
+                        P->ell_col[slot] = (uint16_t)local;
+                        if (local >= pe - ps) ++nnz_halo;
                     } else {
                         const int64_t slot = er_slot_of(ro, k2++, rr, L);
                         store_value(&P->er_val[(size_t)slot * vb], vb, dt, v);
@@ -459,6 +558,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     P->nnz_ell = nnz_ell;
     P->nnz_er = nnz_er;
     P->n_er_rows = n_er_rows;
+    P->nnz_halo = nnz_halo;
     P->t_encode = now_s() - t0;
     return EHYB_OK;
 }
@@ -480,7 +580,7 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
         if (params) prm = *params;
         Error e = validate(A);
         if (!e.ok()) return fail(e.status, e.msg);
-        if (prm.reserved != 0) return fail(EHYB_EINVAL, "reserved parameter field must be 0");
+        if (prm.halo_rows < -1) return fail(EHYB_EINVAL, "halo_rows must be >= -1");
         if (prm.value_dtype < 0 || prm.value_dtype > 2) return fail(EHYB_EINVAL, "unknown value dtype");
         if (prm.rows_per_wave == 0) prm.rows_per_wave = kWave;
         if (prm.rows_per_wave < 1 || prm.rows_per_wave > kWave ||
@@ -510,7 +610,7 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
         P->kc = kEllKC;
         // LDS per partition row: its x element and its residual accumulator
         const int64_t tau = 2 * (int64_t)P->xbytes;
-        const int64_t max_rows = std::min<int64_t>(65535, prm.lds_bytes / tau);
+        const int64_t max_rows = std::min<int64_t>(65535, (prm.lds_bytes - kStaticLds) / tau);
         if (max_rows < 1) return fail(EHYB_EINVAL, "lds_bytes smaller than one partition row");
         // Eq. 1-2: smallest K with n*tau/(K*P) < SHM, VecSize = ceil(n/(K*P))
         int64_t K = 1;
@@ -544,7 +644,21 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
             if (!pe.ok()) return fail(pe.status, pe.msg);
             P->t_partition = now_s() - t0;
         }
-        ehyb_status st = build_plan(A, part, nparts, P.get());
+        // halo room: the LDS vector holds x-slice + halo, plus one residual
+        // accumulator per row
+        int32_t halo_cap = 0;
+        if (prm.halo_rows >= 0) {
+            int32_t maxp = 0;
+            {
+                std::vector<int32_t> sizes(nparts, 0);
+                for (int64_t i = 0; i < n; ++i) sizes[part[i]]++;
+                for (int32_t s2 : sizes) maxp = std::max(maxp, s2);
+            }
+            const int64_t room = (int64_t)(prm.lds_bytes - kStaticLds) / P->xbytes - 2 * (int64_t)maxp;
+            halo_cap = (int32_t)std::max<int64_t>(0, std::min<int64_t>(room, 65535 - (int64_t)maxp));
+            if (prm.halo_rows > 0) halo_cap = std::min(halo_cap, prm.halo_rows);
+        }
+        ehyb_status st = build_plan(A, part, nparts, halo_cap, P.get());
         if (st != EHYB_OK) return st;
         *out = P.release();
         return EHYB_OK;
@@ -565,6 +679,10 @@ ehyb_status ehyb_plan_stats_get(const ehyb_plan* P, ehyb_plan_stats* out) {
     out->ell_slots = P->ell_slots;
     out->er_slots = P->er_slots;
     out->n_er_rows = P->n_er_rows;
+    out->nnz_halo = P->nnz_halo;
+    out->n_halo = (int64_t)P->halo_idx.size();
+    out->max_halo = P->max_halo;
+    out->lds_bytes_used = (int32_t)lds_bytes_used(*P);
     out->device_bytes = (int64_t)compute_layout(*P).total;
     out->algorithmic_bytes = algorithmic_bytes(*P);
     out->nparts = P->nparts;
@@ -600,6 +718,10 @@ ehyb_status ehyb_plan_arrays_get(const ehyb_plan* P, ehyb_plan_arrays* out) {
     out->part_start = P->part_start.data();
     out->slice_start = P->slice_start.data();
     out->er_slice_start = P->er_slice_start.data();
+    out->ell_free = P->ell_free.data();
+    out->halo_start = P->halo_start.data();
+    out->halo_idx = P->halo_idx.data();
+    out->n_halo = (int64_t)P->halo_idx.size();
     out->ell_meta = P->ell_meta.data();
     out->er_meta = P->er_meta.data();
     out->er_row = P->er_row.data();
@@ -623,7 +745,7 @@ ehyb_status ehyb_plan_decode_csr(const ehyb_plan* P, int64_t* row_ptr, int32_t* 
         const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
         for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
             const int64_t eo = P->ell_meta[4 * (size_t)s + 0];
-            const int32_t r0 = ps + (s - P->slice_start[p]) * C;
+            const int32_t r0 = ps + (int32_t)(P->ell_meta[4 * (size_t)s + 1] >> 16) * C;
             for (int32_t r = 0; r < C && r0 + r < pe; ++r) {
                 const int32_t row = r0 + r;
                 int64_t out_at = row_ptr[row];
@@ -635,7 +757,11 @@ ehyb_status ehyb_plan_decode_csr(const ehyb_plan* P, int64_t* row_ptr, int32_t* 
                 while (a < na || b < nb) {
                     const int64_t sa = a < na ? ell_slot_of(eo, a, r, L, kc) : 0;
                     const int64_t sb = b < nb ? er_slot_of(ro, b, rr, L) : 0;
-                    const int32_t ca = a < na ? ps + P->ell_col[sa] : INT32_MAX;
+                    int32_t ca = INT32_MAX;
+                    if (a < na) {
+                        const int32_t lc = P->ell_col[sa];
+                        ca = lc < pe - ps ? ps + lc : P->halo_idx[P->halo_start[p] + lc - (pe - ps)];
+                    }
                     const int32_t cb = b < nb ? P->er_col[sb] : INT32_MAX;
                     if (ca < cb) {
                         col_idx[out_at] = ca;
@@ -665,13 +791,13 @@ void ehyb_plan_destroy(ehyb_plan* P) { delete P; }
 }  // extern "C"
 
 // ------------------------------------------------------------- plan files
-// Layout: magic "EHYBPLN2", u32 version, then fixed header fields and arrays
+// Layout: magic "EHYBPLN4", u32 version, then fixed header fields and arrays
 // (each prefixed by its u64 byte length), then a u64 FNV-1a checksum of all
 // preceding bytes.
 
 namespace {
-const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '2'};
-const uint32_t kVersion = 2;
+const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '4'};
+const uint32_t kVersion = 4;
 
 uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
     for (size_t i = 0; i < n; ++i) {
@@ -726,6 +852,7 @@ const char* validate_loaded(const ehyb_plan& P) {
     const int C = P.C;
     if (P.perm.size() != n || P.part_start.size() != (size_t)P.nparts + 1 ||
         P.slice_start.size() != (size_t)P.nparts + 1 || P.er_slice_start.size() != (size_t)P.nparts + 1 ||
+        P.ell_free.size() != (size_t)P.nparts || P.halo_start.size() != (size_t)P.nparts + 1 ||
         P.ell_meta.size() != (size_t)P.nslices * 4 || P.er_meta.size() != (size_t)P.ner_slices * 2 ||
         P.er_row.size() != (size_t)P.ner_slices * C ||
         P.ell_val.size() != (size_t)P.ell_slots * P.vbytes || P.ell_col.size() != (size_t)P.ell_slots ||
@@ -737,20 +864,42 @@ const char* validate_loaded(const ehyb_plan& P) {
                          P.er_slice_start[P.nparts] != P.ner_slices))
         return "plan file partition bounds are inconsistent";
     if (P.nparts == 0 && n != 0) return "plan file has rows but no partitions";
-    const int64_t max_rows = std::min<int64_t>(65535, (int64_t)(160 * 1024) / (2 * P.xbytes));
+    if (P.nparts > 0 && (P.halo_start[0] != 0 || (size_t)P.halo_start[P.nparts] != P.halo_idx.size()))
+        return "plan file halo bounds are inconsistent";
+    int32_t maxh = 0;
+    for (int32_t p = 0; p < P.nparts; ++p) {
+        const int32_t hs = P.halo_start[p], he = P.halo_start[p + 1];
+        if (he < hs) return "plan file halo bounds decrease";
+        maxh = std::max(maxh, he - hs);
+        for (int32_t k = hs; k < he; ++k) {
+            const int32_t j = P.halo_idx[k];
+            if (j < 0 || (size_t)j >= n || (j >= P.part_start[p] && j < P.part_start[p + 1]) ||
+                (k > hs && j <= P.halo_idx[k - 1]))
+                return "plan file halo is invalid";
+        }
+    }
+    if (maxh != P.max_halo) return "plan file largest halo is inconsistent";
+    if (lds_bytes_used(P) > 160 * 1024 - kStaticLds) return "plan file needs more LDS than a workgroup has";
+    const int64_t max_rows = std::min<int64_t>(65535, (int64_t)(160 * 1024 - kStaticLds) / (2 * P.xbytes));
     for (int32_t p = 0; p < P.nparts; ++p) {
         const int64_t sz = (int64_t)P.part_start[p + 1] - P.part_start[p];
         const int64_t sl = (int64_t)P.slice_start[p + 1] - P.slice_start[p];
         const int64_t el = (int64_t)P.er_slice_start[p + 1] - P.er_slice_start[p];
         if (sz <= 0 || sz > max_rows || sl != (sz + C - 1) / C || el < 0 || el > sl)
             return "plan file partition sizes are inconsistent";
+        if (P.ell_free[p] < 0 || P.ell_free[p] > sl) return "plan file ELL free-slice count is inconsistent";
+        std::vector<char> seen_j((size_t)sl, 0);
         for (int32_t s = P.slice_start[p]; s < P.slice_start[p + 1]; ++s) {
-            const uint64_t eo = P.ell_meta[4 * (size_t)s], es = P.ell_meta[4 * (size_t)s + 1];
+            const uint64_t eo = P.ell_meta[4 * (size_t)s], es = P.ell_meta[4 * (size_t)s + 1] & 0xFFFFu;
+            const int64_t j = P.ell_meta[4 * (size_t)s + 1] >> 16;
+            if (j >= sl || seen_j[(size_t)j]) return "plan file ELL slice indices are not a permutation";
+            seen_j[(size_t)j] = 1;
             if (eo + es * kWave * P.kc > (uint64_t)P.ell_slots) return "plan file ELL slot range out of bounds";
+            const int64_t ext = sz + P.halo_start[p + 1] - P.halo_start[p];
             for (uint64_t q = eo; q < eo + es * kWave * P.kc; ++q)
-                if (P.ell_col[q] >= sz) return "plan file ELL column outside its slice";
+                if (P.ell_col[q] >= ext) return "plan file ELL column outside its LDS vector";
             const uint64_t mask = (uint64_t)P.ell_meta[4 * (size_t)s + 2] | ((uint64_t)P.ell_meta[4 * (size_t)s + 3] << 32);
-            const int64_t rows = std::min<int64_t>(C, sz - (int64_t)(s - P.slice_start[p]) * C);
+            const int64_t rows = std::min<int64_t>(C, sz - j * C);
             if (rows < 64 && (mask >> rows) != 0) return "plan file residual mask names a missing row";
         }
         for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e) {
@@ -799,10 +948,15 @@ ehyb_status ehyb_plan_save(const ehyb_plan* P, const char* path) {
         w.pod(P->nnz_ell);
         w.pod(P->nnz_er);
         w.pod(P->n_er_rows);
+        w.pod(P->nnz_halo);
+        w.pod(P->max_halo);
         w.vec(P->perm);
         w.vec(P->part_start);
         w.vec(P->slice_start);
         w.vec(P->er_slice_start);
+        w.vec(P->ell_free);
+        w.vec(P->halo_start);
+        w.vec(P->halo_idx);
         w.vec(P->ell_meta);
         w.vec(P->er_meta);
         w.vec(P->er_row);
@@ -865,6 +1019,8 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.pod(P->nnz_ell);
         r.pod(P->nnz_er);
         r.pod(P->n_er_rows);
+        r.pod(P->nnz_halo);
+        r.pod(P->max_halo);
         if (!r.ok || P->n < 0 || P->n > INT32_MAX || P->nparts < 0 || P->nslices < 0 || P->ner_slices < 0 ||
             P->value_dtype < 0 || P->value_dtype > 2 || P->L < 1 || P->L > kWave || P->C * P->L != kWave ||
             P->kc != kEllKC || P->ell_slots < 0 || P->er_slots < 0 || P->max_part_rows < 0)
@@ -876,6 +1032,9 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.vec(P->part_start, lim);
         r.vec(P->slice_start, lim);
         r.vec(P->er_slice_start, lim);
+        r.vec(P->ell_free, lim);
+        r.vec(P->halo_start, lim);
+        r.vec(P->halo_idx, lim);
         r.vec(P->ell_meta, lim);
         r.vec(P->er_meta, lim);
         r.vec(P->er_row, lim);

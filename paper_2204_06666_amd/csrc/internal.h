@@ -13,6 +13,7 @@ namespace ehyb {
 constexpr int kWave = 64;              // gfx950 wavefront width
 constexpr int kEllKC = 2;              // ELL entries per lane per load step
 constexpr size_t kBlobAlign = 256;
+constexpr int kStaticLds = 64;         // LDS the SpMV kernel keeps for its queue counters
 
 // Undirected graph in CSR form with vertex and edge weights.
 struct Graph {
@@ -38,7 +39,8 @@ Error partition_multilevel(const Graph& g, int32_t nparts, int64_t cap, uint64_t
 
 // Byte offsets of each array inside the device blob.
 struct BlobLayout {
-    size_t part_start = 0, slice_start = 0, er_slice_start = 0;
+    size_t part_start = 0, slice_start = 0, er_slice_start = 0, ell_free = 0;
+    size_t halo_start = 0, halo_idx = 0;
     size_t ell_meta = 0, er_meta = 0, er_row = 0;
     size_t ell_val = 0, ell_col = 0, er_val = 0, er_col = 0;
     size_t perm = 0, xp = 0, yp = 0;
@@ -62,7 +64,10 @@ struct ehyb_plan {
     std::vector<int32_t> part_start;      // [nparts+1]
     std::vector<int32_t> slice_start;     // [nparts+1] ELL slices
     std::vector<int32_t> er_slice_start;  // [nparts+1] residual slices
-    std::vector<uint32_t> ell_meta;       // [4*nslices] off, steps, er mask lo, hi
+    std::vector<int32_t> ell_free;        // [nparts] leading ELL slices without residual rows
+    std::vector<int32_t> halo_start;      // [nparts+1]
+    std::vector<int32_t> halo_idx;        // cached neighbour x entries (permuted global indices)
+    std::vector<uint32_t> ell_meta;       // [4*nslices] off, steps | index << 16, er mask lo, hi
     std::vector<uint32_t> er_meta;        // [2*ner_slices] off, steps
     std::vector<uint16_t> er_row;         // [C*ner_slices] local row, 0xFFFF = none
     std::vector<int32_t> er_pos;          // [n] permuted row -> e*C + r in the residual part, -1
@@ -72,7 +77,8 @@ struct ehyb_plan {
     std::vector<int32_t> er_col;          // er_slots
     std::vector<int32_t> row_ell_len, row_er_len;  // [n], permuted rows
     int64_t ell_slots = 0, er_slots = 0;
-    int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0;
+    int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0, nnz_halo = 0;
+    int32_t max_halo = 0;
     double t_graph = 0, t_partition = 0, t_reorder = 0, t_encode = 0;
     int32_t launch_waves = 0;      // 0 = automatic launch shape
     // device binding (non-owning)
@@ -87,4 +93,5 @@ ehyb_status fail(ehyb_status st, const std::string& msg);
 ehyb_status ok();
 BlobLayout compute_layout(const ehyb_plan& p);
 int64_t algorithmic_bytes(const ehyb_plan& p);
+int64_t lds_bytes_used(const ehyb_plan& p);
 }  // namespace ehyb

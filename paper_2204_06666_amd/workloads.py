@@ -22,5 +22,10 @@ HEADLINE_PARAMS = {
     "slice_rows": 0,
     "rows_per_wave": 64,
     "ell_width_cap": 0,
+    "halo_rows": 0,        # neighbour x entries cached in LDS as far as it allows
     "seed": 0,
 }
+
+# The paper's split: every entry outside the partition goes to the residual
+# part and reads x from device memory.
+PAPER_SPLIT_PARAMS = dict(HEADLINE_PARAMS, halo_rows=-1)

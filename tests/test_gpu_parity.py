@@ -8,7 +8,7 @@ import pytest
 import matgen
 import oracle
 from paper_2204_06666_amd import EhybError, Plan, _abi, csr_spmv, probe_copy, probe_read
-from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS
+from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS, PAPER_SPLIT_PARAMS
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -45,19 +45,19 @@ def _check(A, x, y, what):
 
 
 @pytest.mark.parametrize("rpw", [64, 32, 16, 8, 4, 2, 1])
-@pytest.mark.parametrize("permuted", [True, False])
-def test_config1_parity(torch, rpw, permuted):
+@pytest.mark.parametrize("permuted,halo", [(True, 0), (False, 0), (True, -1)])
+def test_config1_parity(torch, rpw, permuted, halo):
     A = matgen.config_matrix(1)
     x = matgen.uniform_vector(A.n_rows, matgen.CONFIG_SEEDS[1] + 2)
-    y, _ = _ehyb(torch, A, x, permuted, rows_per_wave=rpw)
+    y, _ = _ehyb(torch, A, x, permuted, rows_per_wave=rpw, halo_rows=halo)
     _check(A, x, y, f"cfg1 rpw={rpw} permuted={permuted}")
 
 
-@pytest.mark.parametrize("rpw", [64, 8])
-def test_integer_poisson_bit_exact(torch, rpw):
+@pytest.mark.parametrize("rpw,halo", [(64, 0), (8, -1), (64, -1)])
+def test_integer_poisson_bit_exact(torch, rpw, halo):
     A = matgen.config_matrix(1)
     x = matgen.integer_vector(A.n_rows, 77)
-    y, _ = _ehyb(torch, A, x, rows_per_wave=rpw, slice_rows=300)
+    y, _ = _ehyb(torch, A, x, rows_per_wave=rpw, slice_rows=300, halo_rows=halo)
     print(f"[parity] integer poisson rpw={rpw}", flush=True)
     assert np.array_equal(y, oracle.spmv(A, x))
 
@@ -76,12 +76,13 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("rpw", [64, 16, 4])
-def test_matrix_families(torch, name, make, kw, rpw):
+@pytest.mark.parametrize("rpw,halo", [(64, 0), (64, -1), (16, 0), (4, -1), (16, 24)])
+def test_matrix_families(torch, name, make, kw, rpw, halo):
     A = make()
     x = matgen.uniform_vector(A.n_rows, 123)
-    y, P = _ehyb(torch, A, x, rows_per_wave=rpw, **kw)
-    _check(A, x, y, f"{name} rpw={rpw} parts={P.stats()['nparts']}")
+    y, P = _ehyb(torch, A, x, rows_per_wave=rpw, halo_rows=halo, **kw)
+    st = P.stats()
+    _check(A, x, y, f"{name} rpw={rpw} halo={halo} parts={st['nparts']} er={st['nnz_er']}")
 
 
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 129])
@@ -99,9 +100,10 @@ def test_all_empty_rows_give_positive_zero(torch):
     assert np.all(y == 0) and not np.signbit(y).any()
 
 
-def test_bitwise_determinism(torch):
+@pytest.mark.parametrize("halo", [0, -1])
+def test_bitwise_determinism(torch, halo):
     A = matgen.stencil3d(40, perm_seed=11, val_seed=12)
-    P = Plan(A, slice_rows=3000).upload("cuda:0")
+    P = Plan(A, slice_rows=3000, halo_rows=halo).upload("cuda:0")
     x = _dev(torch, matgen.uniform_vector(A.n_rows, 13))
     y0 = P.spmv(x).clone()
     for _ in range(20):
@@ -141,6 +143,9 @@ def test_headline_full_size(torch):
     print(f"[parity] headline worst scaled error {w:.2e} stats {P.stats()['nparts']} parts", flush=True)
     y2, _ = _ehyb(torch, A, x, permuted=False, **HEADLINE_PARAMS)
     _check(A, x, y2, "headline unpermuted")
+    y3, P3 = _ehyb(torch, A, x, **PAPER_SPLIT_PARAMS)
+    assert P3.stats()["nnz_er"] > 0
+    _check(A, x, y3, "headline, paper split (residual part read from device memory)")
     # the comparator on the same input
     rp = _dev(torch, A.row_ptr.astype(np.int32))
     yc = torch.empty(A.n_rows, dtype=torch.float64, device="cuda:0")

@@ -13,9 +13,9 @@ from oracle.structure import check_plan, layout_spmv
 from paper_2204_06666_amd import EhybError, Plan, _abi
 
 
-def _full_check(A, plan, value_dtype=np.float64, width_cap=0, x_seed=7, tau_x=16):
+def _full_check(A, plan, value_dtype=np.float64, width_cap=0, x_seed=7, x_bytes=8):
     v = plan.arrays()
-    st = check_plan(A, v, width_cap=width_cap, value_dtype=value_dtype, tau_x=tau_x)
+    st = check_plan(A, v, width_cap=width_cap, value_dtype=value_dtype, x_bytes=x_bytes)
     perm = v["perm"]
     # decode == P A P^T, values bit for bit
     rp, ci, val = plan.decode()
@@ -45,10 +45,10 @@ CASES = [
 
 
 @pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
-@pytest.mark.parametrize("rpw", [64, 16, 1])
-def test_plan_structure_and_roundtrip(name, make, kw, rpw):
+@pytest.mark.parametrize("rpw,halo", [(64, 0), (16, -1), (1, 0), (64, 7)])
+def test_plan_structure_and_roundtrip(name, make, kw, rpw, halo):
     A = make()
-    P = Plan(A, rows_per_wave=rpw, **kw)
+    P = Plan(A, rows_per_wave=rpw, halo_rows=halo, **kw)
     st = _full_check(A, P)
     s = P.stats()
     assert s["nnz_ell"] == st["nnz_ell"] and s["nnz_er"] == st["nnz_er"]
@@ -76,7 +76,7 @@ def test_block_diagonal_has_no_residual():
     """Connected blocks no larger than a partition: a good partitioner cuts no
     edge, so the residual part is empty."""
     A = matgen.block_diagonal([100] * 6, seed=5, density=0.1)
-    P = Plan(A, slice_rows=100, imbalance_pct=1)
+    P = Plan(A, slice_rows=100, imbalance_pct=1, halo_rows=-1)
     st = _full_check(A, P)
     assert st["nnz_er"] == 0
 
@@ -85,8 +85,8 @@ def test_partitioner_beats_scrambled_blocks():
     """Configuration 1 is randomly relabelled: consecutive blocks of the given
     order cut almost everything, the graph partitioner very little."""
     A = matgen.config_matrix(1)
-    nat = Plan(A, slice_rows=512, partitioner=1).stats()
-    ml = Plan(A, slice_rows=512).stats()
+    nat = Plan(A, slice_rows=512, partitioner=1, halo_rows=-1).stats()
+    ml = Plan(A, slice_rows=512, halo_rows=-1).stats()
     assert nat["nnz_er"] / nat["nnz"] > 0.5
     assert ml["nnz_er"] / ml["nnz"] < 0.08
 
@@ -117,7 +117,7 @@ def test_determinism_same_seed():
     A = matgen.stencil3d(14, perm_seed=2, val_seed=3)
     a = Plan(A, slice_rows=400, seed=5).arrays()
     b = Plan(A, slice_rows=400, seed=5).arrays()
-    for k in ("perm", "part_start", "ell_val", "ell_col", "er_col", "ell_meta", "er_meta", "er_row"):
+    for k in ("perm", "part_start", "ell_val", "ell_col", "er_col", "ell_meta", "er_meta", "er_row", "ell_free"):
         assert np.array_equal(a[k], b[k]), k
 
 
@@ -138,7 +138,7 @@ def test_tiny_and_empty():
 def test_fp32_plan_values_rounded():
     A = matgen.stencil3d(10, perm_seed=1, val_seed=2)
     P = Plan(A, slice_rows=300, value_dtype=1)
-    _full_check(A, P, value_dtype=np.float32, tau_x=8)
+    _full_check(A, P, value_dtype=np.float32, x_bytes=4)
 
 
 @pytest.mark.parametrize("mutate,status", [
@@ -220,7 +220,8 @@ def test_algorithmic_bytes_formula():
     P = Plan(A, slice_rows=400)
     s = P.stats()
     want = (s["ell_slots"] * 10 + s["er_slots"] * 12 + s["nslices"] * 16
-            + s["ner_slices"] * (8 + 2 * s["rows_per_slice"]) + (s["nparts"] + 1) * 12 + 2 * s["n"] * 8)
+            + s["ner_slices"] * (8 + 2 * s["rows_per_slice"]) + (s["nparts"] + 1) * 16 + s["nparts"] * 4
+            + s["n_halo"] * 4 + 2 * s["n"] * 8)
     assert s["algorithmic_bytes"] == want
 
 
@@ -231,3 +232,48 @@ def test_host_threads_do_not_change_the_plan():
     for k in ("perm", "ell_val", "ell_col", "er_val", "er_col", "ell_meta", "er_meta", "er_row"):
         assert np.array_equal(a[k], b[k]), k
     assert os.environ.get("OMP_NUM_THREADS", "") == os.environ.get("OMP_NUM_THREADS", "")
+
+
+def test_halo_caches_all_neighbours_of_a_stencil():
+    """With room in LDS every out-of-partition entry of a stencil is served
+    from the halo: the residual part is empty and the halo holds exactly the
+    distinct external columns."""
+    A = matgen.stencil3d(16, perm_seed=3, val_seed=4)
+    P = Plan(A, slice_rows=800)
+    st = _full_check(A, P)
+    s = P.stats()
+    assert s["nnz_er"] == 0 and st["nnz_er"] == 0
+    none = Plan(A, slice_rows=800, halo_rows=-1).stats()
+    assert s["nnz_halo"] == none["nnz_er"] > 0
+    assert none["n_halo"] == 0 and none["nnz_halo"] == 0
+
+
+def test_halo_cap_keeps_most_referenced_columns():
+    A = matgen.stencil3d(14, perm_seed=5, val_seed=6)
+    cap = 40
+    P = Plan(A, slice_rows=700, halo_rows=cap)
+    _full_check(A, P)
+    v = P.arrays()
+    assert np.diff(v["halo_start"]).max() <= cap
+    B = oracle.permute(A, v["perm"])
+    ps = v["part_start"]
+    rows = np.repeat(np.arange(A.n_rows), np.diff(B.row_ptr))
+    for p in range(len(ps) - 1):
+        sel = (rows >= ps[p]) & (rows < ps[p + 1])
+        c = B.col[sel]
+        ext = c[(c < ps[p]) | (c >= ps[p + 1])]
+        cols, counts = np.unique(ext, return_counts=True)
+        h = v["halo_idx"][v["halo_start"][p]:v["halo_start"][p + 1]]
+        inh = np.isin(cols, h)
+        assert inh.sum() == min(cap, cols.size)
+        if (~inh).any() and inh.any():
+            assert counts[inh].min() >= counts[~inh].max()
+
+
+@pytest.mark.parametrize("sr", [3907, 7800, 10200])
+def test_lds_budget_respected_at_the_limit(sr):
+    """Plans near the LDS limit must leave room for the kernel's own counters."""
+    A = matgen.stencil3d(30, perm_seed=1, val_seed=2)
+    P = Plan(A, slice_rows=min(sr, A.n_rows))
+    s = P.stats()
+    assert s["lds_bytes_used"] <= 160 * 1024 - 64

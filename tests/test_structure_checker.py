@@ -33,6 +33,8 @@ def _tiny():
     er_row[0, 0], er_row[1, 0] = 0, 1
     view = dict(n=4, nparts=2, L=1, kc=2, perm=np.arange(4), part_start=np.array([0, 2, 4]),
                 slice_start=np.array([0, 1, 2]), er_slice_start=np.array([0, 1, 2]),
+                ell_free=np.array([0, 0]), halo_start=np.array([0, 0, 0]),
+                halo_idx=np.zeros(0, dtype=np.int32),
                 ell_meta=np.array([[0, 1, 0b01, 0], [128, 1, 0b10, 0]], dtype=np.uint32),
                 er_meta=np.array([[0, 1], [64, 1]], dtype=np.uint32), er_row=er_row,
                 ell_val=ell_val, ell_col=ell_col, er_val=er_val, er_col=er_col,
@@ -57,7 +59,9 @@ def test_hand_built_plan_passes():
     (lambda v: v["perm"].__setitem__(slice(0, 2), [1, 0]), ""),
     (lambda v: v["row_er_len"].__setitem__(0, 0), ""),
     (lambda v: v["ell_meta"].__setitem__((1, 0), 0), "overlapping"),
-    (lambda v: v["ell_meta"].__setitem__((0, 2), 0), "mask"),
+    (lambda v: v["ell_meta"].__setitem__((0, 2), 0b10), "mask"),
+    (lambda v: v["ell_meta"].__setitem__((0, 2), 0), "queue order"),
+    (lambda v: v["ell_free"].__setitem__(0, 1), "queue order"),
     (lambda v: v["er_row"].__setitem__((1, 0), 0), ""),
     (lambda v: v["er_meta"].__setitem__((1, 1), 2), ""),
     (lambda v: v["part_start"].__setitem__(1, 3), ""),
@@ -90,4 +94,4 @@ def test_intra_partition_entry_in_residual_is_caught():
 def test_lds_budget_and_16bit_limit():
     A, _, view = _tiny()
     with pytest.raises(PlanError, match="on-chip"):
-        check_plan(A, view, tau_x=8, lds_budget=8)
+        check_plan(A, view, x_bytes=8, lds_budget=8)
