@@ -85,11 +85,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "knn-fem"],
+                    help="stencil27: the headline FP64 product (default); knn-fem: the "
+                         "unstructured-FEM matrix in FP64, FP32 and BF16 values")
+    ap.add_argument("--scale", type=float, default=1.0,
+                    help="knn-fem only: fraction of the 1e6 points")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the EHYB kernel runs on one device, "
               "multi-GPU sharding is a design note, not a benchmark here", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "knn-fem":
+        return run_precision(args)
 
     import numpy as np
     import torch
@@ -253,6 +260,69 @@ def main():
         "preprocess_s": round(t_pre, 2),
         "preprocess_over_spmv": round(t_pre / wall, 0),
         "kernel_source_sha256_16": kh,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_precision(args):
+    """Unstructured-FEM matrix (mutual kNN, 3x3 blocks): FP64 values against
+    FP32 and BF16 values with binary32 x and accumulation, each with its error
+    against the FP64 oracle."""
+    import numpy as np
+    import torch
+
+    import matgen
+    import oracle
+    from oracle.precision import quantize
+    from paper_2204_06666_amd import EHYB_BF16, EHYB_F32, EHYB_F64, Plan
+
+    dev = torch.device("cuda:0")
+    log(f"generating the kNN-FEM matrix (scale {args.scale})")
+    A = matgen.config_matrix(3, scale=args.scale)
+    x = matgen.uniform_vector(A.n_rows, matgen.CONFIG_SEEDS[3] + 2)
+    n, nnz = A.n_rows, A.nnz
+    flops = 2.0 * nnz
+    log(f"n={n} nnz={nnz}; FP64 oracle")
+    y64 = oracle.spmv(A, x)
+    s64 = oracle.abs_scale(A, x)
+    res = {}
+    for name, dt in (("f64", EHYB_F64), ("f32", EHYB_F32), ("bf16", EHYB_BF16)):
+        log(f"preprocessing {name}")
+        t0 = time.perf_counter()
+        plan = Plan(A, value_dtype=dt).upload(dev)
+        t_pre = time.perf_counter() - t0
+        st = plan.stats()
+        perm = plan.perm()
+        xt = torch.from_numpy(x[perm].astype(np.float64 if dt == EHYB_F64 else np.float32)).to(dev)
+        yt = torch.empty_like(xt)
+        wall, kern = time_launches(torch, lambda: plan.spmv(xt, yt), args.steps, args.warmup)
+        yp = yt.cpu().numpy().astype(np.float64)
+        y = np.empty_like(yp)
+        y[perm] = yp
+        e = oracle.scaled_error(y, y64, s64)
+        res[name] = {"GFLOPs": round(flops / wall / 1e9, 2), "us_per_step": round(wall * 1e6, 2),
+                     "algorithmic_bytes": st["algorithmic_bytes"],
+                     "algorithmic_GBps": round(st["algorithmic_bytes"] / kern / 1e9, 1),
+                     "pct_of_8TBps": round(100 * st["algorithmic_bytes"] / kern / 8e12, 2),
+                     "max_row_scaled_error_vs_fp64": float(e.max()),
+                     "normwise_rel_error_vs_fp64": float(np.linalg.norm(y - y64) / np.linalg.norm(y64)),
+                     "nparts": st["nparts"], "nnz_er": st["nnz_er"], "nnz_halo": st["nnz_halo"],
+                     "preprocess_s": round(t_pre, 2)}
+        if dt != EHYB_F64:
+            Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, name))
+            xq = x.astype(np.float32).astype(np.float64)
+            eq = oracle.scaled_error(y, oracle.spmv(Aq, xq), oracle.abs_scale(Aq, xq))
+            res[name]["max_row_scaled_error_vs_quantized"] = float(eq.max())
+        log(f"{name}: {res[name]}")
+        del plan, xt, yt
+    out = {
+        "metric": METRIC, "value": res["f64"]["GFLOPs"], "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["f64"]["us_per_step"] / 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"mutual-kNN FEM stand-in, {int(1_000_000 * args.scale)} points ~U[0,1]^3, "
+                               f"k ~ U{{12..40}}, 3x3 blocks (seeds 3000-3003)", "n": n, "nnz": nnz},
+        "precision": res,
     }
     print(json.dumps(out), flush=True)
 

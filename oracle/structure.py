@@ -150,12 +150,20 @@ def layout_entries(view):
     return tuple(np.concatenate([o[i] for o in out]) for i in range(4))
 
 
+def stored_values_f64(view, vals) -> np.ndarray:
+    """Stored values as float64 (bfloat16 plans keep bit patterns)."""
+    if int(view.get("value_dtype", 0)) == 2:
+        from .precision import bf16_bits_to_f64
+        return bf16_bits_to_f64(vals)
+    return np.asarray(vals).astype(np.float64)
+
+
 def layout_spmv(view, xp: np.ndarray) -> np.ndarray:
     """Execute the EHYB arrays as laid out (a sequential format interpreter):
     y_p = sum over real slots of the row of val * xp[col], in permuted space."""
     row, col, val, _ = layout_entries(view)
     n = int(view["n"])
-    return np.bincount(row, weights=val.astype(np.float64) * xp[col], minlength=n)
+    return np.bincount(row, weights=stored_values_f64(view, val) * xp[col], minlength=n)
 
 
 def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_cap: int = 0,
@@ -163,8 +171,8 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
     """Check every structural property of an EHYB encoding of ``A``.
 
     ``value_dtype`` is the storage type of values (float64 plans must reproduce
-    A's bits; lower-precision plans must reproduce A's values rounded to that
-    type).  ``Bperm`` may pass a precomputed P A P^T.  Returns statistics."""
+    A's bits; float32 and "bf16" plans must reproduce A's values rounded to
+    nearest-even in that type).  ``Bperm`` may pass a precomputed P A P^T.  Returns statistics."""
     from . import permute
 
     n = int(view["n"])
@@ -323,7 +331,11 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
     _req(row.size == B.nnz, f"entry count {row.size} != nnz {B.nnz}")
     _req(np.array_equal(row, Brows) and np.array_equal(col, B.col.astype(np.int64)),
          "stored pattern differs from P A P^T")
-    want = B.val.astype(value_dtype)
+    if isinstance(value_dtype, str) and value_dtype == "bf16":
+        from .precision import to_bf16_bits
+        want = to_bf16_bits(B.val)
+    else:
+        want = B.val.astype(value_dtype)
     _req(np.array_equal(np.ascontiguousarray(val).view(np.uint8),
                         np.ascontiguousarray(want).view(np.uint8)),
          "stored values differ from P A P^T bit for bit")

@@ -64,7 +64,8 @@ class Plan:
         self._blob = None
         if _handle is not None:
             self._h = _handle
-            self.n = self.stats()["n"]
+            st = self.stats()
+            self.n, self.value_dtype = st["n"], st["value_dtype"]
             return
         rp, ci, v = _as_csr(A)
         csr = _abi.CsrHost(A.n_rows, A.n_cols, int(rp[-1]) if rp.size else 0,
@@ -75,6 +76,7 @@ class Plan:
         check(self._lib.ehyb_preprocess(ctypes.byref(csr), ctypes.byref(prm), ctypes.byref(self._h)),
               "ehyb_preprocess")
         self.n = int(A.n_rows)
+        self.value_dtype = int(value_dtype)
 
     # ------------------------------------------------------------ host side
     def __del__(self):
@@ -170,15 +172,22 @@ class Plan:
         self.device = blob.device
         return self
 
+    @property
+    def x_dtype(self):
+        """torch dtype of x and y: float64 for FP64 plans, float32 otherwise."""
+        import torch
+        return torch.float64 if self.value_dtype == EHYB_F64 else torch.float32
+
     def spmv(self, x, y=None, permuted: bool = True, stream=None):
         """y = A x.  ``permuted``: x and y are in the plan's order."""
         import torch
         n = self.n
         if y is None:
             y = torch.empty(n, dtype=x.dtype, device=x.device)
+        want = self.x_dtype
         for t in (x, y):
-            if t.dtype != torch.float64 or not t.is_contiguous() or t.numel() != n or not t.is_cuda:
-                raise ValueError("x and y must be contiguous float64 CUDA tensors of length n")
+            if t.dtype != want or not t.is_contiguous() or t.numel() != n or not t.is_cuda:
+                raise ValueError(f"x and y must be contiguous {want} CUDA tensors of length n")
         check(self._lib.ehyb_spmv(self._h, _ptr(x), _ptr(y), EHYB_VEC_PERMUTED if permuted else 0,
                                   _stream(stream)), "ehyb_spmv")
         return y

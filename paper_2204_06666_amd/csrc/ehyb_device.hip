@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -23,7 +24,7 @@ __device__ __forceinline__ int xcd_logical_id(int b, int nblocks) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-struct SpmvF64Args {
+struct SpmvArgs {
     const int32_t* part_start;      // [nparts+1] first permuted row of each partition
     const int32_t* slice_start;     // [nparts+1] first ELL row-slice of each partition
     const int32_t* er_slice_start;  // [nparts+1] first residual row-slice of each partition
@@ -33,22 +34,83 @@ struct SpmvF64Args {
     const uint4* ell_meta;          // slot offset, steps | index << 16, residual-row mask (lo, hi)
     const uint2* er_meta;           // slot offset, steps
     const uint16_t* er_row;         // local row of each residual slice row, 0xFFFF = none
-    const double* ell_val;
+    const void* ell_val;            // value type of the plan
     const uint16_t* ell_col;
-    const double* er_val;
+    const void* er_val;
     const int32_t* er_col;
-    const double* x;                // permuted order
-    double* y;                      // permuted order
+    const void* x;                  // permuted order, x type of the plan
+    void* y;                        // permuted order
     int32_t lds_rows;               // LDS elements before the residual accumulators
 };
 
-constexpr int kEllChunk = 16;   // ELL steps whose loads are issued before any is used
-constexpr int kErChunk = 16;    // residual steps likewise
+constexpr int kErChunk = 16;    // residual steps whose loads are issued before any is used
 constexpr int kStageRegs = 4;   // 16-byte x-slice loads per thread kept in flight
 constexpr int kHaloRegs = 2;    // halo gathers per thread kept in flight
 
-template <int L>
-__device__ __forceinline__ double reduce_lanes(double v) {
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xFFFF0000u); }
+
+// Per value type: storage (V), x and accumulator types (X, A), ELL entries
+// per lane per step (KC: 16 bytes of values), the per-step value and column
+// loads (VL, CL), how many steps are loaded before use (kEll), and one step's
+// multiply-adds against the LDS vector.
+template <int DT> struct Prec;
+
+template <> struct Prec<EHYB_F64> {
+    using V = double;
+    using X = double;
+    using A = double;
+    using VL = double2;
+    using CL = uint32_t;
+    static constexpr int KC = 2;
+    static constexpr int kEll = 16;
+    __device__ static __forceinline__ void step(const VL& v, CL c, const X* xs, A& acc) {
+        acc = fma(v.x, xs[c & 0xFFFFu], acc);
+        acc = fma(v.y, xs[c >> 16], acc);
+    }
+    __device__ static __forceinline__ A value(V v) { return v; }
+};
+
+template <> struct Prec<EHYB_F32> {
+    using V = float;
+    using X = float;
+    using A = float;
+    using VL = float4;
+    using CL = uint2;
+    static constexpr int KC = 4;
+    static constexpr int kEll = 16;
+    __device__ static __forceinline__ void step(const VL& v, CL c, const X* xs, A& acc) {
+        acc = fmaf(v.x, xs[c.x & 0xFFFFu], acc);
+        acc = fmaf(v.y, xs[c.x >> 16], acc);
+        acc = fmaf(v.z, xs[c.y & 0xFFFFu], acc);
+        acc = fmaf(v.w, xs[c.y >> 16], acc);
+    }
+    __device__ static __forceinline__ A value(V v) { return v; }
+};
+
+template <> struct Prec<EHYB_BF16> {
+    using V = uint16_t;  // bfloat16 bits
+    using X = float;
+    using A = float;
+    using VL = uint4;    // eight bfloat16 values
+    using CL = uint4;    // eight 16-bit columns
+    static constexpr int KC = 8;
+    static constexpr int kEll = 8;
+    __device__ static __forceinline__ void step(const VL& v, CL c, const X* xs, A& acc) {
+        acc = fmaf(bf16_lo(v.x), xs[c.x & 0xFFFFu], acc);
+        acc = fmaf(bf16_hi(v.x), xs[c.x >> 16], acc);
+        acc = fmaf(bf16_lo(v.y), xs[c.y & 0xFFFFu], acc);
+        acc = fmaf(bf16_hi(v.y), xs[c.y >> 16], acc);
+        acc = fmaf(bf16_lo(v.z), xs[c.z & 0xFFFFu], acc);
+        acc = fmaf(bf16_hi(v.z), xs[c.z >> 16], acc);
+        acc = fmaf(bf16_lo(v.w), xs[c.w & 0xFFFFu], acc);
+        acc = fmaf(bf16_hi(v.w), xs[c.w >> 16], acc);
+    }
+    __device__ static __forceinline__ A value(V v) { return __uint_as_float((uint32_t)v << 16); }
+};
+
+template <int L, class T>
+__device__ __forceinline__ T reduce_lanes(T v) {
     if constexpr (L > 1) {
 #pragma unroll
         for (int off = L / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
@@ -107,12 +169,22 @@ __device__ __forceinline__ void wave_wait(int* ctr, int target) {
 // streaming.  The sum of a row is (ELL entries in column order) + (residual
 // entries in column order), fixed by the plan: results are bitwise
 // reproducible.
-template <int L>
-__global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
-    extern __shared__ double lds[];
+template <int DT, int L>
+__global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
+    using P = Prec<DT>;
+    using V = typename P::V;
+    using X = typename P::X;
+    using Acc = typename P::A;
+    using VL = typename P::VL;
+    using CL = typename P::CL;
+    constexpr int KC = P::KC;
+    constexpr int kEll = P::kEll;
+    constexpr int XV = 16 / (int)sizeof(X);  // x elements per 16-byte load
+    extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ int q_er, q_ell, n_staged, n_er_done;
-    double* xs = lds;
-    double* yer = lds + a.lds_rows;
+    X* xs = reinterpret_cast<X*>(lds_raw);
+    Acc* yer = reinterpret_cast<Acc*>(xs + a.lds_rows);
+    const X* __restrict__ x = static_cast<const X*>(a.x);
     constexpr int C = kWave / L;
     const int p = xcd_logical_id(blockIdx.x, gridDim.x);
     const int ps = a.part_start[p];
@@ -128,14 +200,17 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
         n_er_done = 0;
     }
 
-    // 1. x-slice into LDS (16-byte loads over the aligned body)
+    // 1. x-slice into LDS (16-byte loads over the aligned body), then the halo
     {
-        const double* src = a.x + ps;
-        const int head = (int)(((uintptr_t)src >> 3) & 1);  // 1 if src is 8- but not 16-byte aligned
-        const int h = head < sz ? head : sz;
-        const int nvec = (sz - h) >> 1;
-        const double2* src2 = reinterpret_cast<const double2*>(src + h);
-        double2 stg[kStageRegs];
+        const X* src = x + ps;
+        int h = (int)(((16 - ((uintptr_t)src & 15)) & 15) / sizeof(X));  // elements before 16-byte alignment
+        h = h < sz ? h : sz;
+        const int nvec = (sz - h) / XV;
+        // 16-byte global loads; LDS stores element by element (the LDS
+        // destination xs + h is only element-aligned)
+        typedef X XL __attribute__((ext_vector_type(16 / sizeof(X))));
+        const XL* src2 = reinterpret_cast<const XL*>(src + h);
+        XL stg[kStageRegs];
 #pragma unroll
         for (int j = 0; j < kStageRegs; ++j) {
             const int i = tid + j * nthr;
@@ -145,17 +220,17 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
         for (int j = 0; j < kStageRegs; ++j) {
             const int i = tid + j * nthr;
             if (i < nvec) {
-                xs[h + 2 * i] = stg[j].x;
-                xs[h + 2 * i + 1] = stg[j].y;
+#pragma unroll
+                for (int k = 0; k < XV; ++k) xs[h + XV * i + k] = stg[j][k];
             }
         }
         for (int i = tid + kStageRegs * nthr; i < nvec; i += nthr) {
-            const double2 v = src2[i];
-            xs[h + 2 * i] = v.x;
-            xs[h + 2 * i + 1] = v.y;
+            const XL v = src2[i];
+#pragma unroll
+            for (int k = 0; k < XV; ++k) xs[h + XV * i + k] = v[k];
         }
-        if (tid < h) xs[0] = src[0];
-        const int tail = h + 2 * nvec;
+        if (tid < h) xs[tid] = src[tid];
+        const int tail = h + XV * nvec;
         if (tid < sz - tail) xs[tail + tid] = src[tail + tid];
         // halo after the x-slice: index loads, then gathers
         const int hs = a.halo_start[p];
@@ -166,18 +241,18 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
             const int i = tid + j * nthr;
             if (i < hn) hi[j] = a.halo_idx[hs + i];
         }
-        double hv[kHaloRegs];
+        X hv[kHaloRegs];
 #pragma unroll
         for (int j = 0; j < kHaloRegs; ++j) {
             const int i = tid + j * nthr;
-            if (i < hn) hv[j] = a.x[hi[j]];
+            if (i < hn) hv[j] = x[hi[j]];
         }
 #pragma unroll
         for (int j = 0; j < kHaloRegs; ++j) {
             const int i = tid + j * nthr;
             if (i < hn) xs[sz + i] = hv[j];
         }
-        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr) xs[sz + i] = a.x[a.halo_idx[hs + i]];
+        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr) xs[sz + i] = x[a.halo_idx[hs + i]];
     }
     __syncthreads();  // counters initialised, x-slice and halo in LDS
 
@@ -185,6 +260,7 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
     const int e0 = a.er_slice_start[p];
     const int ner = a.er_slice_start[p + 1] - e0;
     {
+        const V* er_val = static_cast<const V*>(a.er_val);
         int it = wave_fetch_add(&q_er, lane);
         uint2 m = it < ner ? a.er_meta[e0 + it] : make_uint2(0, 0);
         while (it < ner) {
@@ -192,13 +268,14 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
             const uint2 mn = itn < ner ? a.er_meta[e0 + itn] : make_uint2(0, 0);
             const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
             const uint32_t steps = __builtin_amdgcn_readfirstlane(m.y);
-            const double* ev = a.er_val + off + lane;
+            const V* ev = er_val + off + lane;
             const int32_t* ec = a.er_col + off + lane;
             const uint16_t lr = a.er_row[(size_t)(e0 + it) * C + r];
-            double acc = 0.0;
+            Acc acc = 0;
             for (uint32_t t0 = 0; t0 < steps; t0 += kErChunk) {
                 int32_t c[kErChunk];
-                double v[kErChunk], xg[kErChunk];
+                V v[kErChunk];
+                X xg[kErChunk];
 #pragma unroll
                 for (int j = 0; j < kErChunk; ++j)
                     if (t0 + j < steps) {
@@ -207,10 +284,10 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
                     }
 #pragma unroll
                 for (int j = 0; j < kErChunk; ++j)
-                    if (t0 + j < steps) xg[j] = a.x[c[j]];
+                    if (t0 + j < steps) xg[j] = x[c[j]];
 #pragma unroll
                 for (int j = 0; j < kErChunk; ++j)
-                    if (t0 + j < steps) acc = fma(v[j], xg[j], acc);
+                    if (t0 + j < steps) acc = fma(P::value(v[j]), xg[j], acc);
             }
             acc = reduce_lanes<L>(acc);
             if ((lane & (L - 1)) == 0 && lr != 0xFFFF) yer[lr] = acc;
@@ -221,6 +298,8 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
     }
 
     // 3. ELL queue
+    const V* ell_val = static_cast<const V*>(a.ell_val);
+    X* y = static_cast<X*>(a.y);
     const int s0 = a.slice_start[p];
     const int ns = a.slice_start[p + 1] - s0;
     bool er_ready = ner == 0;
@@ -233,24 +312,21 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
         const uint4 mu = uniform4(m);
         const uint32_t steps = mu.y & 0xFFFFu;
         const int j0 = (int)(mu.y >> 16);
-        const double2* v2 = reinterpret_cast<const double2*>(a.ell_val + mu.x) + lane;
-        const uint32_t* c2 = reinterpret_cast<const uint32_t*>(a.ell_col + mu.x) + lane;
-        double acc = 0.0;
-        for (uint32_t t0 = 0; t0 < steps; t0 += kEllChunk) {
-            double2 v[kEllChunk];
-            uint32_t c[kEllChunk];
+        const VL* v2 = reinterpret_cast<const VL*>(ell_val + mu.x) + lane;
+        const CL* c2 = reinterpret_cast<const CL*>(a.ell_col + mu.x) + lane;
+        Acc acc = 0;
+        for (uint32_t t0 = 0; t0 < steps; t0 += kEll) {
+            VL v[kEll];
+            CL c[kEll];
 #pragma unroll
-            for (int j = 0; j < kEllChunk; ++j)
+            for (int j = 0; j < kEll; ++j)
                 if (t0 + j < steps) {
                     v[j] = v2[(size_t)(t0 + j) * kWave];
                     c[j] = c2[(size_t)(t0 + j) * kWave];
                 }
 #pragma unroll
-            for (int j = 0; j < kEllChunk; ++j)
-                if (t0 + j < steps) {
-                    acc = fma(v[j].x, xs[c[j] & 0xFFFFu], acc);
-                    acc = fma(v[j].y, xs[c[j] >> 16], acc);
-                }
+            for (int j = 0; j < kEll; ++j)
+                if (t0 + j < steps) P::step(v[j], c[j], xs, acc);
         }
         acc = reduce_lanes<L>(acc);
         const uint64_t mask = ((uint64_t)mu.w << 32) | mu.z;
@@ -261,11 +337,12 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_f64_kernel(SpmvF64Args a) {
         const int lr = j0 * C + r;
         if ((lane & (L - 1)) == 0 && lr < sz) {
             if ((mask >> r) & 1u) acc += yer[lr];
-            a.y[ps + lr] = acc;
+            y[ps + lr] = (X)acc;
         }
         item = nxt;
         m = mn;
     }
+    (void)KC;
 }
 
 // Plain CSR SpMV: L lanes per row (rows of a wavefront are consecutive),
@@ -351,17 +428,31 @@ int launch_waves(const ehyb_plan& P) {
     return 16;
 }
 
-template <int L>
-void launch_spmv_f64(const SpmvF64Args& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+template <int DT, int L>
+void launch_spmv(const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
     static bool lds_raised = false;
     if (!lds_raised && lds > 64 * 1024) {
         // allow the full 160 KiB of gfx950 LDS as dynamic shared memory
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&ehyb_spmv_f64_kernel<L>),
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&ehyb_spmv_kernel<DT, L>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - kStaticLds) != hipSuccess)
             (void)hipGetLastError();
         lds_raised = true;
     }
-    hipLaunchKernelGGL(ehyb_spmv_f64_kernel<L>, dim3(nblocks), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((ehyb_spmv_kernel<DT, L>), dim3(nblocks), dim3(threads), lds, s, a);
+}
+
+template <int DT>
+bool launch_spmv_dt(int L, const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+    switch (L) {
+        case 1: launch_spmv<DT, 1>(a, nblocks, threads, lds, s); return true;
+        case 2: launch_spmv<DT, 2>(a, nblocks, threads, lds, s); return true;
+        case 4: launch_spmv<DT, 4>(a, nblocks, threads, lds, s); return true;
+        case 8: launch_spmv<DT, 8>(a, nblocks, threads, lds, s); return true;
+        case 16: launch_spmv<DT, 16>(a, nblocks, threads, lds, s); return true;
+        case 32: launch_spmv<DT, 32>(a, nblocks, threads, lds, s); return true;
+        case 64: launch_spmv<DT, 64>(a, nblocks, threads, lds, s); return true;
+        default: return false;
+    }
 }
 
 bool is_aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
@@ -452,25 +543,24 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     if (!P || !x || !y) return fail(EHYB_EINVAL, "null argument");
     if (flags & ~EHYB_VEC_PERMUTED) return fail(EHYB_EINVAL, "unknown flag");
     if (!P->dev_blob) return fail(EHYB_ESTATE, "plan not uploaded");
-    if (P->value_dtype != EHYB_F64) return fail(EHYB_EUNSUPPORTED, "only FP64 plans have a kernel");
-    if (x == y) return fail(EHYB_EINVAL, "x and y must not overlap");
-    if (!is_aligned(x, 8) || !is_aligned(y, 8)) return fail(EHYB_EINVAL, "x and y must be 8-byte aligned");
-    const size_t vb = (size_t)P->n * 8;
+    const size_t xb = (size_t)P->xbytes;
+    if (!is_aligned(x, xb) || !is_aligned(y, xb)) return fail(EHYB_EINVAL, "x and y must be aligned to their element size");
+    const size_t vb = (size_t)P->n * xb;
     if ((const char*)x < (const char*)y + vb && (const char*)y < (const char*)x + vb)
         return fail(EHYB_EINVAL, "x and y must not overlap");
     if (P->n == 0) return EHYB_OK;
     hipStream_t s = (hipStream_t)stream;
     const char* blob = (const char*)P->dev_blob;
     const BlobLayout& Ly = P->layout;
-    const double* xin = (const double*)x;
-    double* yout = (double*)y;
+    const void* xin = x;
+    void* yout = y;
     if (!(flags & EHYB_VEC_PERMUTED)) {
         ehyb_status st = ehyb_permute_x(P, x, (void*)(blob + Ly.xp), stream);
         if (st != EHYB_OK) return st;
-        xin = (const double*)(blob + Ly.xp);
-        yout = (double*)(blob + Ly.yp);
+        xin = blob + Ly.xp;
+        yout = (void*)(blob + Ly.yp);
     }
-    SpmvF64Args a;
+    SpmvArgs a;
     a.part_start = (const int32_t*)(blob + Ly.part_start);
     a.slice_start = (const int32_t*)(blob + Ly.slice_start);
     a.er_slice_start = (const int32_t*)(blob + Ly.er_slice_start);
@@ -480,9 +570,9 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     a.ell_meta = (const uint4*)(blob + Ly.ell_meta);
     a.er_meta = (const uint2*)(blob + Ly.er_meta);
     a.er_row = (const uint16_t*)(blob + Ly.er_row);
-    a.ell_val = (const double*)(blob + Ly.ell_val);
+    a.ell_val = blob + Ly.ell_val;
     a.ell_col = (const uint16_t*)(blob + Ly.ell_col);
-    a.er_val = (const double*)(blob + Ly.er_val);
+    a.er_val = blob + Ly.er_val;
     a.er_col = (const int32_t*)(blob + Ly.er_col);
     a.x = xin;
     a.y = yout;
@@ -490,17 +580,16 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     const int nblocks = P->nparts;
     const size_t lds = (size_t)lds_bytes_used(*P);
     if (lds > 160 * 1024 - kStaticLds) return fail(EHYB_EUNSUPPORTED, "partition and halo larger than the LDS budget");
+    if (P->kc != kc_for(P->value_dtype)) return fail(EHYB_EINVAL, "plan chunk width does not match its value type");
     const int threads = launch_waves(*P) * kWave;
-    switch (P->L) {
-        case 1: launch_spmv_f64<1>(a, nblocks, threads, lds, s); break;
-        case 2: launch_spmv_f64<2>(a, nblocks, threads, lds, s); break;
-        case 4: launch_spmv_f64<4>(a, nblocks, threads, lds, s); break;
-        case 8: launch_spmv_f64<8>(a, nblocks, threads, lds, s); break;
-        case 16: launch_spmv_f64<16>(a, nblocks, threads, lds, s); break;
-        case 32: launch_spmv_f64<32>(a, nblocks, threads, lds, s); break;
-        case 64: launch_spmv_f64<64>(a, nblocks, threads, lds, s); break;
-        default: return fail(EHYB_EINVAL, "bad lanes per row");
+    bool ok = false;
+    switch (P->value_dtype) {
+        case EHYB_F64: ok = launch_spmv_dt<EHYB_F64>(P->L, a, nblocks, threads, lds, s); break;
+        case EHYB_F32: ok = launch_spmv_dt<EHYB_F32>(P->L, a, nblocks, threads, lds, s); break;
+        case EHYB_BF16: ok = launch_spmv_dt<EHYB_BF16>(P->L, a, nblocks, threads, lds, s); break;
+        default: break;
     }
+    if (!ok) return fail(EHYB_EINVAL, "bad lanes per row or value type");
     ehyb_status st = launch_status("ehyb_spmv");
     if (st != EHYB_OK) return st;
     if (!(flags & EHYB_VEC_PERMUTED)) return ehyb_unpermute_y(P, yout, y, stream);

@@ -607,7 +607,7 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
         P->xbytes = prm.value_dtype == EHYB_F64 ? 8 : 4;
         P->C = prm.rows_per_wave;
         P->L = kWave / prm.rows_per_wave;
-        P->kc = kEllKC;
+        P->kc = kc_for(prm.value_dtype);
         // LDS per partition row: its x element and its residual accumulator
         const int64_t tau = 2 * (int64_t)P->xbytes;
         const int64_t max_rows = std::min<int64_t>(65535, (prm.lds_bytes - kStaticLds) / tau);
@@ -1023,7 +1023,7 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.pod(P->max_halo);
         if (!r.ok || P->n < 0 || P->n > INT32_MAX || P->nparts < 0 || P->nslices < 0 || P->ner_slices < 0 ||
             P->value_dtype < 0 || P->value_dtype > 2 || P->L < 1 || P->L > kWave || P->C * P->L != kWave ||
-            P->kc != kEllKC || P->ell_slots < 0 || P->er_slots < 0 || P->max_part_rows < 0)
+            P->kc != kc_for(P->value_dtype) || P->ell_slots < 0 || P->er_slots < 0 || P->max_part_rows < 0)
             return fail(EHYB_EINVAL, "plan file header is inconsistent");
         P->vbytes = P->value_dtype == EHYB_F64 ? 8 : (P->value_dtype == EHYB_F32 ? 4 : 2);
         P->xbytes = P->value_dtype == EHYB_F64 ? 8 : 4;

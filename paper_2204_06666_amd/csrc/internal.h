@@ -11,7 +11,8 @@
 namespace ehyb {
 
 constexpr int kWave = 64;              // gfx950 wavefront width
-constexpr int kEllKC = 2;              // ELL entries per lane per load step
+// ELL entries per lane per load step: 16 bytes of values (FP64 2, FP32 4, BF16 8)
+constexpr int kc_for(int value_dtype) { return value_dtype == EHYB_F64 ? 2 : (value_dtype == EHYB_F32 ? 4 : 8); }
 constexpr size_t kBlobAlign = 256;
 constexpr int kStaticLds = 64;         // LDS the SpMV kernel keeps for its queue counters
 
@@ -52,7 +53,7 @@ struct BlobLayout {
 struct ehyb_plan {
     int64_t n = 0, nnz = 0;
     ehyb_params params{};          // resolved parameters
-    int32_t L = 1, C = 64, kc = ehyb::kEllKC;
+    int32_t L = 1, C = 64, kc = 2;
     int32_t nparts = 0, nslices = 0, ner_slices = 0;
     int32_t value_dtype = EHYB_F64;
     int32_t vbytes = 8;            // bytes per stored value

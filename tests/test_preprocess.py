@@ -21,9 +21,10 @@ def _full_check(A, plan, value_dtype=np.float64, width_cap=0, x_seed=7, x_bytes=
     rp, ci, val = plan.decode()
     B = oracle.permute(A, perm)
     assert np.array_equal(rp, B.row_ptr) and np.array_equal(ci, B.col)
-    want = B.val.astype(value_dtype).astype(np.float64)
+    from oracle.precision import quantize
+    want = quantize(B.val, {np.float64: "f64", np.float32: "f32"}.get(value_dtype, value_dtype))
     assert np.array_equal(val.view(np.uint64), want.view(np.uint64))
-    if value_dtype == np.float64:
+    if value_dtype is np.float64:
         x = matgen.uniform_vector(A.n_rows, x_seed)
         yp = layout_spmv(v, x[perm])
         oracle.assert_close(yp, oracle.spmv(A, x)[perm], oracle.abs_scale(A, x)[perm], what="layout")
@@ -135,10 +136,24 @@ def test_tiny_and_empty():
     assert P.stats()["nnz"] == 0
 
 
-def test_fp32_plan_values_rounded():
+@pytest.mark.parametrize("dt,vt,kc", [(1, np.float32, 4), (2, "bf16", 8)])
+@pytest.mark.parametrize("halo", [0, -1])
+def test_low_precision_plan_values_rounded(dt, vt, kc, halo):
+    """FP32 and BF16 plans store each value rounded to nearest even directly
+    from FP64 (checked bit for bit by the oracle's own rounding), with 16
+    bytes of values per lane per step."""
     A = matgen.stencil3d(10, perm_seed=1, val_seed=2)
-    P = Plan(A, slice_rows=300, value_dtype=1)
-    _full_check(A, P, value_dtype=np.float32, x_bytes=4)
+    P = Plan(A, slice_rows=300, value_dtype=dt, halo_rows=halo)
+    assert P.stats()["kc"] == kc
+    _full_check(A, P, value_dtype=vt, x_bytes=4)
+    v = P.arrays()
+    from oracle.precision import quantize
+    from oracle.structure import layout_spmv
+    x = matgen.uniform_vector(A.n_rows, 3)
+    perm = v["perm"]
+    Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, "f32" if dt == 1 else "bf16"))
+    yq = oracle.spmv(Aq, x)[perm]
+    oracle.assert_close(layout_spmv(v, x[perm]), yq, oracle.abs_scale(Aq, x)[perm], what="quantized layout")
 
 
 @pytest.mark.parametrize("mutate,status", [
