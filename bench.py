@@ -85,9 +85,11 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "knn-fem"],
+    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "knn-fem", "batched"],
                     help="stencil27: the headline FP64 product (default); knn-fem: the "
-                         "unstructured-FEM matrix in FP64, FP32 and BF16 values")
+                         "unstructured-FEM matrix in FP64, FP32 and BF16 values; batched: 64 "
+                         "uneven FP32 matrices x 8 right-hand sides in one launch")
+    ap.add_argument("--count", type=int, default=64, help="batched only: number of matrices")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="knn-fem only: fraction of the 1e6 points")
     args = ap.parse_args()
@@ -97,6 +99,8 @@ def main():
         sys.exit(2)
     if args.workload == "knn-fem":
         return run_precision(args)
+    if args.workload == "batched":
+        return run_batched(args)
 
     import numpy as np
     import torch
@@ -323,6 +327,151 @@ def run_precision(args):
         "config": {"workload": f"mutual-kNN FEM stand-in, {int(1_000_000 * args.scale)} points ~U[0,1]^3, "
                                f"k ~ U{{12..40}}, 3x3 blocks (seeds 3000-3003)", "n": n, "nnz": nnz},
         "precision": res,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_batched(args):
+    """64 matrices of uneven sizes (2-D Poisson, 27-point stencil, kNN-FEM),
+    8 right-hand sides each, FP32 values, x and accumulation: one persistent
+    launch over all (matrix, partition) work items, recorded in a HIP graph,
+    against 64 x 8 separate single-vector products of plans built for one
+    right-hand side."""
+    import numpy as np
+    import torch
+
+    import matgen
+    import oracle
+    from oracle.precision import gamma32, quantize
+    from paper_2204_06666_amd import EHYB_F32, Batch, Plan
+
+    nrhs = 8
+    dev = torch.device("cuda:0")
+    log(f"generating {args.count} matrices")
+    mats = []
+    for i, fm in enumerate(matgen.batch_matrices(args.count)):
+        mats.append(fm)
+        if i % 16 == 15:
+            log(f"  {i + 1} matrices generated")
+    sum_n = sum(A.n_rows for _, A in mats)
+    sum_nnz = sum(A.nnz for _, A in mats)
+    log(f"sum n={sum_n} sum nnz={sum_nnz}; preprocessing (n_rhs={nrhs} plans)")
+    t0 = time.perf_counter()
+    plans = []
+    for i, (_, A) in enumerate(mats):
+        plans.append(Plan(A, value_dtype=EHYB_F32, n_rhs=nrhs).upload(dev))
+        if i % 16 == 15:
+            log(f"  {i + 1} plans built")
+    t_pre = time.perf_counter() - t0
+    B = Batch(plans, nrhs, dev)
+    g = matgen.rng(4999)
+    X = [g.uniform(-1.0, 1.0, (A.n_rows, nrhs)) for _, A in mats]
+    Xd = [torch.from_numpy(x[p.perm()].astype(np.float32)).to(dev) for x, p in zip(X, plans)]
+    Yd = [torch.empty_like(x) for x in Xd]
+    flops = 2.0 * sum_nnz * nrhs
+    algo = sum(p.stats()["algorithmic_bytes"] + 2 * (nrhs - 1) * p.n * 4 for p in plans)
+
+    log("batched launch, eager")
+    wall_e, kern_e = time_launches(torch, lambda: B.spmm(Xd, Yd), args.steps, args.warmup)
+    log("batched launch, recorded in a HIP graph")
+    cs = torch.cuda.Stream()
+    cs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cs):
+        B.spmm(Xd, Yd)
+    torch.cuda.current_stream().wait_stream(cs)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=cs):
+        B.spmm(Xd, Yd, stream=cs)
+    wall_g, kern_g = time_launches(torch, graph.replay, args.steps, args.warmup)
+    torch.cuda.synchronize()
+
+    # accuracy: every matrix against the FP64 product of the stored (binary32)
+    # values and binary32 x, within the binary32 accumulation bound
+    log("checking all matrices against the oracle")
+    worst = 0.0
+    for i, ((_, A), p, x, y) in enumerate(zip(mats, plans, X, Yd)):
+        if i % 16 == 15:
+            log(f"  {i + 1} matrices checked")
+        Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, "f32"))
+        xq = x.astype(np.float32).astype(np.float64)
+        ref = oracle.spmm(Aq, xq)
+        sc = oracle.spmm(matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, np.abs(Aq.val)), np.abs(xq))
+        got = np.empty_like(ref)
+        got[p.perm()] = y.cpu().numpy()
+        bound = gamma32(np.diff(A.row_ptr) + 2)[:, None] * sc
+        err = np.abs(got - ref)
+        if not np.all((err <= bound) | ((sc == 0) & (got == ref))):
+            raise SystemExit("batched result outside the binary32 accumulation bound")
+        worst = max(worst, float(np.max(err / np.where(sc > 0, sc, 1.0))))
+
+    log("separate products: plans for one right-hand side, 8 launches per matrix")
+    single = []
+    for i, (_, A) in enumerate(mats):
+        single.append(Plan(A, value_dtype=EHYB_F32).upload(dev))
+        if i % 16 == 15:
+            log(f"  {i + 1} single-vector plans built")
+    xs = [torch.from_numpy(np.ascontiguousarray(x[p.perm()].T).astype(np.float32)).to(dev)
+          for x, p in zip(X, single)]
+    ys = [torch.empty_like(x) for x in xs]
+
+    def separate():
+        for p, x, y in zip(single, xs, ys):
+            for r in range(nrhs):
+                p.spmv(x[r], y[r])
+    steps_sep = max(5, args.steps // 10)
+    wall_s, kern_s = time_launches(torch, separate, steps_sep, max(2, args.warmup // 10))
+    gs = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cs):
+        separate()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(gs, stream=cs):
+        separate()
+    wall_sg, kern_sg = time_launches(torch, gs.replay, steps_sep, max(2, args.warmup // 10))
+    # the separate products must agree with the batched one within twice the bound
+    for (_, A), p1, pb, y1, yb in zip(mats[:8], single, plans, ys, Yd):
+        a = np.empty((A.n_rows, nrhs))
+        a[p1.perm()] = y1.cpu().numpy().T
+        b = np.empty((A.n_rows, nrhs))
+        b[pb.perm()] = yb.cpu().numpy()
+        assert np.allclose(a, b, rtol=1e-4, atol=1e-4)
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle on the first matrices (bounded sample)")
+        t0 = time.perf_counter()
+        done_nnz, used = 0, []
+        for (_, A), x in zip(mats, X):
+            oracle.spmm(A, x)
+            done_nnz += A.nnz
+            used.append(A.n_rows)
+            if time.perf_counter() - t0 > args.cpu_seconds:
+                break
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(2.0 * done_nnz * nrhs / t_cpu / 1e9, 3), "unit": "GFLOP/s",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"FP64 CSR x 8 right-hand sides over the first {len(used)} matrices "
+                         f"({done_nnz} nnz), one pass"}
+    out = {
+        "metric": "batched EHYB SpMM GFLOP/s, 64 uneven matrices x 8 RHS, FP32",
+        "value": round(flops / wall_g / 1e9, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall_g * 1e3, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.count} matrices, n log-uniform in [1e4, 5e5], 2-D Poisson / "
+                               f"27-point stencil / kNN-FEM 3 dof (seeds 4000+i), 8 RHS ~ U[-1,1], FP32",
+                   "sum_n": sum_n, "sum_nnz": sum_nnz, "work_items": sum(p.stats()["nparts"] for p in plans)},
+        "roofline": {"bound": "hbm", "achieved": round(algo / kern_g / 1e9, 1), "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": round(algo / kern_g / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "algorithmic_bytes": algo, "launch_us": round(kern_g * 1e6, 2)},
+        "cpu_baseline": cpu,
+        "batched_eager_us": round(wall_e * 1e6, 2),
+        "batched_graph_us": round(wall_g * 1e6, 2),
+        "separate_eager_us": round(wall_s * 1e6, 2),
+        "separate_graph_us": round(wall_sg * 1e6, 2),
+        "speedup_vs_separate_graph": round(wall_sg / wall_g, 2),
+        "max_row_scaled_error_vs_quantized": worst,
+        "preprocess_s": round(t_pre, 1),
     }
     print(json.dumps(out), flush=True)
 

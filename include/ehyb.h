@@ -106,6 +106,12 @@ typedef struct {
                                many, -1 = none, so that every entry outside the
                                partition goes to the residual part (the
                                paper's split) */
+    int32_t n_rhs;          /* right-hand sides the plan is sized for: the LDS
+                               budget holds n_rhs x elements per row (tau of
+                               Eq. 1 grows n_rhs-fold); 0 = 1.  A plan for
+                               n_rhs > 1 also runs ehyb_spmv; ehyb_spmm_batched
+                               needs plans built for its n_rhs */
+    int32_t reserved;       /* must be 0 */
     uint64_t seed;          /* partitioner seed (deterministic for a seed) */
 } ehyb_params;
 
@@ -136,6 +142,8 @@ typedef struct {
     int32_t eq1_K;            /* K of Eq. 1 for this n (informational) */
     int32_t max_halo;         /* largest halo of one partition */
     int32_t lds_bytes_used;   /* LDS one workgroup of ehyb_spmv uses */
+    int32_t n_rhs;            /* right-hand sides the plan is sized for */
+    int32_t reserved2;
     double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */
 } ehyb_plan_stats;
 
@@ -252,6 +260,37 @@ EHYB_API ehyb_status ehyb_plan_set_launch(ehyb_plan *plan, int32_t waves_per_wg)
  * reordering applied to vectors; FP64 for FP64 plans). */
 EHYB_API ehyb_status ehyb_permute_x(const ehyb_plan *plan, const void *x, void *x_perm, void *stream);
 EHYB_API ehyb_status ehyb_unpermute_y(const ehyb_plan *plan, const void *y_perm, void *y, void *stream);
+
+/* ---- Batched products (several matrices, several right-hand sides) ----
+ *
+ * A batch groups uploaded plans of one value type, one rows_per_wave and one
+ * n_rhs.  ehyb_spmm_batched computes Y_i = A_i X_i for every matrix i in one
+ * persistent kernel launch: workgroups take (matrix, partition) items, largest
+ * first, from a queue in the batch's device blob (the global queue of Alg. 3,
+ * spread over matrices); the last workgroup to finish resets the queue, so
+ * the launch can be recorded in a HIP graph and replayed.  X_i and Y_i are
+ * row-major [n_i][n_rhs] in plan i's permuted order (flag EHYB_VEC_PERMUTED
+ * required), element type as for ehyb_spmv. */
+typedef struct ehyb_batch ehyb_batch;
+
+#define EHYB_BATCH_MAX 128   /* matrices per batch */
+
+/* Group `n_plans` plans (host pointers, borrowed: they must outlive the batch
+ * and stay uploaded to the same blobs).  Every plan must have the same value
+ * type, rows_per_wave and n_rhs == `n_rhs` (1, 2, 4 or 8). */
+EHYB_API ehyb_status ehyb_batch_create(const ehyb_plan *const *plans, int32_t n_plans, int32_t n_rhs,
+                                      ehyb_batch **out);
+/* Device bytes of the batch descriptor (per-matrix array pointers, work items, queue counters). */
+EHYB_API ehyb_status ehyb_batch_device_bytes(const ehyb_batch *batch, size_t *bytes);
+/* Copy the batch descriptor into `dev_blob` (device, caller-owned, 256-byte
+ * aligned); the plans must be uploaded first.  Waits for the copy. */
+EHYB_API ehyb_status ehyb_batch_upload(ehyb_batch *batch, void *dev_blob, size_t bytes, void *stream);
+/* Y_i = A_i X_i for all matrices of the batch, one kernel launch on `stream`.
+ * X, Y: host arrays of n_plans device pointers.  Launches on one batch blob
+ * must not overlap in time (they share its queue counters). */
+EHYB_API ehyb_status ehyb_spmm_batched(const ehyb_batch *batch, int32_t n_rhs, const void *const *X,
+                                      void *const *Y, uint32_t flags, void *stream);
+EHYB_API void ehyb_batch_destroy(ehyb_batch *batch);
 
 /* Save / load a plan (host arrays only) as a versioned binary file with a
  * checksum; a loaded plan must be uploaded before use.  A corrupted or

@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "Csr", "rng", "poisson2d", "stencil3d", "knn_fem", "powerlaw", "random_small",
     "uniform_vector", "integer_vector", "block_diagonal", "from_dense", "to_dense",
-    "config_matrix", "CONFIG_SEEDS",
+    "config_matrix", "CONFIG_SEEDS", "batch_matrices",
 ]
 
 
@@ -343,3 +343,25 @@ def config_matrix(cfg: int, scale: float = 1.0) -> Csr:
         return knn_fem(max(100, int(1_000_000 * scale)), 12, 40, 3,
                        perm_seed=s, pt_seed=s + 3, val_seed=s + 1)
     raise ValueError(f"no matrix recipe for configuration {cfg}")
+
+
+def batch_matrices(count: int = 64, seed: int = 4000, n_lo: int = 10_000, n_hi: int = 500_000):
+    """The uneven batch: matrix i draws, from generator seed + i, a row count
+    n ~ log-uniform [n_lo, n_hi] and a family uniformly among the 2-D 5-point
+    Poisson (side round(sqrt n)), the 27-point 3-D stencil (side round(cbrt n))
+    and the mutual-kNN FEM matrix with 3 dof (n/3 points); every matrix is
+    randomly relabelled.  Returns [(family, Csr)]."""
+    out = []
+    for i in range(count):
+        s = seed + i
+        g = rng(s)
+        n = int(round(np.exp(g.uniform(np.log(n_lo), np.log(n_hi)))))
+        fam = ("poisson2d", "stencil27", "knn3")[int(g.integers(0, 3))]
+        if fam == "poisson2d":
+            A = poisson2d(max(2, int(round(np.sqrt(n)))), perm_seed=s)
+        elif fam == "stencil27":
+            A = stencil3d(max(2, int(round(n ** (1.0 / 3.0)))), perm_seed=s, val_seed=s + 100_000)
+        else:
+            A = knn_fem(max(50, n // 3), perm_seed=s, pt_seed=s + 200_000, val_seed=s + 100_000)
+        out.append((fam, A))
+    return out

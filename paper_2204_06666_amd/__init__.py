@@ -20,7 +20,7 @@ from . import _abi
 from ._abi import (EHYB_BF16, EHYB_F32, EHYB_F64, EHYB_VEC_PERMUTED, EhybError,  # noqa: F401
                    check, load)
 
-__all__ = ["Plan", "csr_spmv", "probe_read", "probe_copy", "device_info", "version",
+__all__ = ["Plan", "Batch", "csr_spmv", "probe_read", "probe_copy", "device_info", "version",
            "EhybError", "EHYB_F64", "EHYB_F32", "EHYB_BF16", "EHYB_VEC_PERMUTED", "load"]
 
 _NP_VAL = {EHYB_F64: np.float64, EHYB_F32: np.float32, EHYB_BF16: np.uint16}
@@ -58,7 +58,8 @@ class Plan:
     def __init__(self, A=None, *, slice_rows: int = 0, ell_width_cap: int = 0,
                  rows_per_wave: int = 0, value_dtype: int = EHYB_F64, lds_bytes: int = 0,
                  num_cus: int = 0, n_threads: int = 0, imbalance_pct: int = 0,
-                 partitioner: int = 0, halo_rows: int = 0, seed: int = 0, _handle=None):
+                 partitioner: int = 0, halo_rows: int = 0, n_rhs: int = 0, seed: int = 0,
+                 _handle=None):
         self._lib = load()
         self._h = ctypes.c_void_p()
         self._blob = None
@@ -72,7 +73,7 @@ class Plan:
                            rp.ctypes.data, ci.ctypes.data if ci.size else None,
                            v.ctypes.data if v.size else None)
         prm = _abi.Params(slice_rows, ell_width_cap, rows_per_wave, value_dtype, lds_bytes,
-                          num_cus, n_threads, imbalance_pct, partitioner, halo_rows, seed)
+                          num_cus, n_threads, imbalance_pct, partitioner, halo_rows, n_rhs, 0, seed)
         check(self._lib.ehyb_preprocess(ctypes.byref(csr), ctypes.byref(prm), ctypes.byref(self._h)),
               "ehyb_preprocess")
         self.n = int(A.n_rows)
@@ -92,7 +93,7 @@ class Plan:
     def stats(self) -> dict:
         st = _abi.PlanStats()
         check(self._lib.ehyb_plan_stats_get(self._h, ctypes.byref(st)), "ehyb_plan_stats_get")
-        return {f: getattr(st, f) for f, _ in st._fields_}
+        return {f: getattr(st, f) for f, _ in st._fields_ if not f.startswith("reserved")}
 
     def arrays(self) -> dict:
         """Copies of the plan's host arrays (the layout of include/ehyb.h)."""
@@ -203,6 +204,52 @@ class Plan:
         y = torch.empty_like(yp) if y is None else y
         check(self._lib.ehyb_unpermute_y(self._h, _ptr(yp), _ptr(y), _stream(stream)), "unpermute_y")
         return y
+
+
+class Batch:
+    """Several uploaded plans (one value type, one rows_per_wave, built for
+    `n_rhs`) multiplied in one persistent kernel launch: Y_i = A_i X_i with X_i,
+    Y_i row-major [n_i][n_rhs] in each plan's permuted order."""
+
+    def __init__(self, plans, n_rhs: int, device="cuda:0", stream=None):
+        import torch
+        self._lib = load()
+        self.plans = list(plans)          # keep the plans (and their blobs) alive
+        self.n_rhs = int(n_rhs)
+        self._h = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        check(self._lib.ehyb_batch_create(arr, len(self.plans), self.n_rhs, ctypes.byref(self._h)),
+              "ehyb_batch_create")
+        b = ctypes.c_size_t()
+        check(self._lib.ehyb_batch_device_bytes(self._h, ctypes.byref(b)), "ehyb_batch_device_bytes")
+        blob = torch.empty(b.value + 256, dtype=torch.uint8, device=device)
+        off = (-blob.data_ptr()) % 256
+        with torch.cuda.device(blob.device):
+            check(self._lib.ehyb_batch_upload(self._h, ctypes.c_void_p(blob.data_ptr() + off), b.value,
+                                              _stream(stream)), "ehyb_batch_upload")
+        self._blob = blob
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self._lib.ehyb_batch_destroy(h)
+            self._h = ctypes.c_void_p()
+
+    def spmm(self, X, Y, stream=None):
+        """Y[i] = A_i X[i] for every matrix (lists of CUDA tensors [n_i, n_rhs])."""
+        k = len(self.plans)
+        if len(X) != k or len(Y) != k:
+            raise ValueError("one X and one Y per matrix")
+        for p, x, y in zip(self.plans, X, Y):
+            for t in (x, y):
+                if (t.dtype != p.x_dtype or not t.is_contiguous() or not t.is_cuda
+                        or tuple(t.shape) != (p.n, self.n_rhs)):
+                    raise ValueError("X[i], Y[i] must be contiguous [n_i, n_rhs] CUDA tensors of the plan's dtype")
+        xs = (ctypes.c_void_p * k)(*[x.data_ptr() for x in X])
+        ys = (ctypes.c_void_p * k)(*[y.data_ptr() for y in Y])
+        check(self._lib.ehyb_spmm_batched(self._h, self.n_rhs, xs, ys, EHYB_VEC_PERMUTED, _stream(stream)),
+              "ehyb_spmm_batched")
+        return Y
 
 
 def csr_spmv(row_ptr32, col, val, x, y, lanes_per_row: int = 0, stream=None):

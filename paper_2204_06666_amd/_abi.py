@@ -26,7 +26,7 @@ class Params(ctypes.Structure):
     _fields_ = [("slice_rows", c_i32), ("ell_width_cap", c_i32), ("rows_per_wave", c_i32),
                 ("value_dtype", c_i32), ("lds_bytes", c_i32), ("num_cus", c_i32),
                 ("n_threads", c_i32), ("imbalance_pct", c_i32), ("partitioner", c_i32),
-                ("halo_rows", c_i32), ("seed", c_u64)]
+                ("halo_rows", c_i32), ("n_rhs", c_i32), ("reserved", c_i32), ("seed", c_u64)]
 
 
 class PlanStats(ctypes.Structure):
@@ -37,7 +37,7 @@ class PlanStats(ctypes.Structure):
                 ("nparts", c_i32), ("nslices", c_i32), ("ner_slices", c_i32), ("slice_rows", c_i32),
                 ("max_part_rows", c_i32), ("rows_per_slice", c_i32), ("lanes_per_row", c_i32),
                 ("kc", c_i32), ("value_dtype", c_i32), ("eq1_K", c_i32),
-                ("max_halo", c_i32), ("lds_bytes_used", c_i32),
+                ("max_halo", c_i32), ("lds_bytes_used", c_i32), ("n_rhs", c_i32), ("reserved2", c_i32),
                 ("t_graph_s", ctypes.c_double), ("t_partition_s", ctypes.c_double),
                 ("t_reorder_s", ctypes.c_double), ("t_encode_s", ctypes.c_double)]
 
@@ -78,6 +78,11 @@ SIGNATURES = {
     "ehyb_probe_read": (c_i32, [c_vp, c_size, c_vp, c_vp]),
     "ehyb_probe_copy": (c_i32, [c_vp, c_vp, c_size, c_vp]),
     "ehyb_device_info_get": (c_i32, [ctypes.POINTER(DeviceInfo)]),
+    "ehyb_batch_create": (c_i32, [ctypes.POINTER(c_vp), c_i32, c_i32, ctypes.POINTER(c_vp)]),
+    "ehyb_batch_device_bytes": (c_i32, [c_vp, ctypes.POINTER(c_size)]),
+    "ehyb_batch_upload": (c_i32, [c_vp, c_vp, c_size, c_vp]),
+    "ehyb_spmm_batched": (c_i32, [c_vp, c_i32, ctypes.POINTER(c_vp), ctypes.POINTER(c_vp), c_u32, c_vp]),
+    "ehyb_batch_destroy": (None, [c_vp]),
     "ehyb_last_error": (ctypes.c_char_p, []),
     "ehyb_version": (ctypes.c_char_p, []),
 }

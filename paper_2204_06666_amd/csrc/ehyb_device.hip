@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <type_traits>
 
 #include "internal.h"
@@ -24,7 +25,8 @@ __device__ __forceinline__ int xcd_logical_id(int b, int nblocks) {
     return xcd < r ? xcd * (q + 1) + idx : r * (q + 1) + (xcd - r) * q + idx;
 }
 
-struct SpmvArgs {
+// Device arrays of one plan (one matrix).
+struct PartArrays {
     const int32_t* part_start;      // [nparts+1] first permuted row of each partition
     const int32_t* slice_start;     // [nparts+1] first ELL row-slice of each partition
     const int32_t* er_slice_start;  // [nparts+1] first residual row-slice of each partition
@@ -38,9 +40,45 @@ struct SpmvArgs {
     const uint16_t* ell_col;
     const void* er_val;
     const int32_t* er_col;
+    int32_t lds_rows;               // LDS rows before the residual accumulators
+    int32_t n;                      // rows
+};
+
+PartArrays part_arrays(const ehyb_plan& P) {
+    const char* blob = (const char*)P.dev_blob;
+    const BlobLayout& Ly = P.layout;
+    PartArrays a;
+    a.part_start = (const int32_t*)(blob + Ly.part_start);
+    a.slice_start = (const int32_t*)(blob + Ly.slice_start);
+    a.er_slice_start = (const int32_t*)(blob + Ly.er_slice_start);
+    a.ell_free = (const int32_t*)(blob + Ly.ell_free);
+    a.halo_start = (const int32_t*)(blob + Ly.halo_start);
+    a.halo_idx = (const int32_t*)(blob + Ly.halo_idx);
+    a.ell_meta = (const uint4*)(blob + Ly.ell_meta);
+    a.er_meta = (const uint2*)(blob + Ly.er_meta);
+    a.er_row = (const uint16_t*)(blob + Ly.er_row);
+    a.ell_val = blob + Ly.ell_val;
+    a.ell_col = (const uint16_t*)(blob + Ly.ell_col);
+    a.er_val = blob + Ly.er_val;
+    a.er_col = (const int32_t*)(blob + Ly.er_col);
+    a.lds_rows = P.max_part_rows + P.max_halo;
+    a.n = (int32_t)P.n;
+    return a;
+}
+
+struct SpmvArgs {
+    PartArrays m;
     const void* x;                  // permuted order, x type of the plan
     void* y;                        // permuted order
-    int32_t lds_rows;               // LDS elements before the residual accumulators
+};
+
+struct BatchArgs {
+    const PartArrays* mats;         // [n_mats]
+    const int2* items;              // (matrix, partition), largest first
+    int32_t n_items;
+    int32_t* counters;              // [0] next item, [1] workgroups finished
+    const void* X[EHYB_BATCH_MAX];  // row-major [n_i][NRHS], permuted order
+    void* Y[EHYB_BATCH_MAX];
 };
 
 constexpr int kErChunk = 16;    // residual steps whose loads are issued before any is used
@@ -52,8 +90,8 @@ __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w 
 
 // Per value type: storage (V), x and accumulator types (X, A), ELL entries
 // per lane per step (KC: 16 bytes of values), the per-step value and column
-// loads (VL, CL), how many steps are loaded before use (kEll), and one step's
-// multiply-adds against the LDS vector.
+// loads (VL, CL), how many steps are loaded before use (kEll), and the
+// unpacking of one step into KC (value, local column) pairs.
 template <int DT> struct Prec;
 
 template <> struct Prec<EHYB_F64> {
@@ -64,9 +102,9 @@ template <> struct Prec<EHYB_F64> {
     using CL = uint32_t;
     static constexpr int KC = 2;
     static constexpr int kEll = 16;
-    __device__ static __forceinline__ void step(const VL& v, CL c, const X* xs, A& acc) {
-        acc = fma(v.x, xs[c & 0xFFFFu], acc);
-        acc = fma(v.y, xs[c >> 16], acc);
+    __device__ static __forceinline__ void unpack(const VL& v, CL c, A (&val)[KC], uint32_t (&col)[KC]) {
+        val[0] = v.x; val[1] = v.y;
+        col[0] = c & 0xFFFFu; col[1] = c >> 16;
     }
     __device__ static __forceinline__ A value(V v) { return v; }
 };
@@ -79,11 +117,9 @@ template <> struct Prec<EHYB_F32> {
     using CL = uint2;
     static constexpr int KC = 4;
     static constexpr int kEll = 16;
-    __device__ static __forceinline__ void step(const VL& v, CL c, const X* xs, A& acc) {
-        acc = fmaf(v.x, xs[c.x & 0xFFFFu], acc);
-        acc = fmaf(v.y, xs[c.x >> 16], acc);
-        acc = fmaf(v.z, xs[c.y & 0xFFFFu], acc);
-        acc = fmaf(v.w, xs[c.y >> 16], acc);
+    __device__ static __forceinline__ void unpack(const VL& v, CL c, A (&val)[KC], uint32_t (&col)[KC]) {
+        val[0] = v.x; val[1] = v.y; val[2] = v.z; val[3] = v.w;
+        col[0] = c.x & 0xFFFFu; col[1] = c.x >> 16; col[2] = c.y & 0xFFFFu; col[3] = c.y >> 16;
     }
     __device__ static __forceinline__ A value(V v) { return v; }
 };
@@ -96,18 +132,27 @@ template <> struct Prec<EHYB_BF16> {
     using CL = uint4;    // eight 16-bit columns
     static constexpr int KC = 8;
     static constexpr int kEll = 8;
-    __device__ static __forceinline__ void step(const VL& v, CL c, const X* xs, A& acc) {
-        acc = fmaf(bf16_lo(v.x), xs[c.x & 0xFFFFu], acc);
-        acc = fmaf(bf16_hi(v.x), xs[c.x >> 16], acc);
-        acc = fmaf(bf16_lo(v.y), xs[c.y & 0xFFFFu], acc);
-        acc = fmaf(bf16_hi(v.y), xs[c.y >> 16], acc);
-        acc = fmaf(bf16_lo(v.z), xs[c.z & 0xFFFFu], acc);
-        acc = fmaf(bf16_hi(v.z), xs[c.z >> 16], acc);
-        acc = fmaf(bf16_lo(v.w), xs[c.w & 0xFFFFu], acc);
-        acc = fmaf(bf16_hi(v.w), xs[c.w >> 16], acc);
+    __device__ static __forceinline__ void unpack(const VL& v, CL c, A (&val)[KC], uint32_t (&col)[KC]) {
+        val[0] = bf16_lo(v.x); val[1] = bf16_hi(v.x); val[2] = bf16_lo(v.y); val[3] = bf16_hi(v.y);
+        val[4] = bf16_lo(v.z); val[5] = bf16_hi(v.z); val[6] = bf16_lo(v.w); val[7] = bf16_hi(v.w);
+        col[0] = c.x & 0xFFFFu; col[1] = c.x >> 16; col[2] = c.y & 0xFFFFu; col[3] = c.y >> 16;
+        col[4] = c.z & 0xFFFFu; col[5] = c.z >> 16; col[6] = c.w & 0xFFFFu; col[7] = c.w >> 16;
     }
     __device__ static __forceinline__ A value(V v) { return __uint_as_float((uint32_t)v << 16); }
 };
+
+// NRHS consecutive elements (one row of a row-major multi-vector).
+template <class T, int N> struct Row {
+    typedef T type __attribute__((ext_vector_type(N)));
+};
+template <class T> struct Row<T, 1> {
+    typedef T type;
+};
+template <class T, int N>
+__device__ __forceinline__ T lane_of(const typename Row<T, N>::type& r, int k) {
+    if constexpr (N == 1) return r;
+    else return r[k];
+}
 
 template <int L, class T>
 __device__ __forceinline__ T reduce_lanes(T v) {
@@ -146,47 +191,56 @@ __device__ __forceinline__ void wave_wait(int* ctr, int target) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// One workgroup per partition (Alg. 3); its wavefronts pull work from two
-// workgroup queues (the balancing of Alg. 3):
+// Counters of the two workgroup queues of one partition.
+struct Queues {
+    int q_er, q_ell, n_staged, n_er_done;
+};
+
+// One partition of one matrix, processed by one workgroup (Alg. 3); its
+// wavefronts pull work from two workgroup queues (the balancing of Alg. 3):
 //  1. the workgroup loads the partition's x-slice into LDS (the cached vector
 //     of Alg. 3) followed by its halo, the x entries of other partitions that
 //     the partition's ELL entries reference;
 //  2. residual queue: a wavefront takes a residual row-slice, loads all its
 //     columns and values (up to kErChunk steps at once), gathers x from
-//     device memory for all of them, and leaves each row's sum in an LDS
-//     accumulator (each residual row belongs to one lane group: plain
+//     device memory for all of them, and leaves each row's sums in LDS
+//     accumulators (each residual row belongs to one lane group: plain
 //     store), then counts the slice.  The next slice's metadata is fetched
 //     while the current one is processed;
 //  3. ELL queue (slices without residual rows first): a wavefront takes a
-//     row-slice, issues all its loads (up to kEllChunk steps of a 16-byte
-//     value pair and a 4-byte column pair per lane) before using any,
-//     multiply-adds against the LDS vector (x-slice and halo) and stores y
-//     once.  A slice with
-//     residual rows first waits until the residual queue is drained, then
-//     adds the residual sums.
+//     row-slice, issues all its loads (up to kEll steps of 16 bytes of values
+//     and KC columns per lane) before using any, multiply-adds against the
+//     LDS vector (x-slice and halo) and stores y once.  A slice with residual
+//     rows first waits until the residual queue is drained, then adds the
+//     residual sums.
 // Wavefronts that leave the residual queue early stream ELL slices while
 // others still gather, so the latency-bound residual work overlaps the
-// streaming.  The sum of a row is (ELL entries in column order) + (residual
-// entries in column order), fixed by the plan: results are bitwise
-// reproducible.
-template <int DT, int L>
-__global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
+// streaming.  With NRHS right-hand sides, x, y and the LDS vector are
+// row-major [row][NRHS] and every entry updates NRHS sums.  The sum of a row
+// is (ELL entries in column order) + (residual entries in column order),
+// fixed by the plan: results are bitwise reproducible.
+// The caller initialises nothing and must not touch LDS or `Q` until every
+// thread has returned (a barrier).
+template <int DT, int L, int NRHS>
+__device__ __forceinline__ void process_partition(const PartArrays& a, int p,
+                                                  const typename Prec<DT>::X* __restrict__ x,
+                                                  typename Prec<DT>::X* __restrict__ y,
+                                                  unsigned char* lds_raw, Queues& Q) {
     using P = Prec<DT>;
     using V = typename P::V;
     using X = typename P::X;
     using Acc = typename P::A;
     using VL = typename P::VL;
     using CL = typename P::CL;
+    using XR = typename Row<X, NRHS>::type;
     constexpr int KC = P::KC;
-    constexpr int kEll = P::kEll;
+    constexpr int kEll = NRHS >= 4 ? (P::kEll > 8 ? P::kEll / 2 : 4) : P::kEll;
+    // residual gathers in flight: whole rows of NRHS elements, about 16 registers' worth each way
+    constexpr int kEr = NRHS == 1 ? kErChunk : (sizeof(X) * NRHS >= 32 ? 4 : 8);
     constexpr int XV = 16 / (int)sizeof(X);  // x elements per 16-byte load
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    __shared__ int q_er, q_ell, n_staged, n_er_done;
-    X* xs = reinterpret_cast<X*>(lds_raw);
-    Acc* yer = reinterpret_cast<Acc*>(xs + a.lds_rows);
-    const X* __restrict__ x = static_cast<const X*>(a.x);
     constexpr int C = kWave / L;
-    const int p = xcd_logical_id(blockIdx.x, gridDim.x);
+    X* xs = reinterpret_cast<X*>(lds_raw);
+    Acc* yer = reinterpret_cast<Acc*>(xs + (size_t)a.lds_rows * NRHS);
     const int ps = a.part_start[p];
     const int sz = a.part_start[p + 1] - ps;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -194,18 +248,19 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
     const int nwaves = nthr >> 6;
     const int r = lane / L;
     if (tid == 0) {
-        q_er = 0;
-        q_ell = 0;
-        n_staged = 0;
-        n_er_done = 0;
+        Q.q_er = 0;
+        Q.q_ell = 0;
+        Q.n_staged = 0;
+        Q.n_er_done = 0;
     }
 
     // 1. x-slice into LDS (16-byte loads over the aligned body), then the halo
     {
-        const X* src = x + ps;
+        const int cnt = sz * NRHS;
+        const X* src = x + (size_t)ps * NRHS;
         int h = (int)(((16 - ((uintptr_t)src & 15)) & 15) / sizeof(X));  // elements before 16-byte alignment
-        h = h < sz ? h : sz;
-        const int nvec = (sz - h) / XV;
+        h = h < cnt ? h : cnt;
+        const int nvec = (cnt - h) / XV;
         // 16-byte global loads; LDS stores element by element (the LDS
         // destination xs + h is only element-aligned)
         typedef X XL __attribute__((ext_vector_type(16 / sizeof(X))));
@@ -231,28 +286,30 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
         }
         if (tid < h) xs[tid] = src[tid];
         const int tail = h + XV * nvec;
-        if (tid < sz - tail) xs[tail + tid] = src[tail + tid];
-        // halo after the x-slice: index loads, then gathers
+        if (tid < cnt - tail) xs[tail + tid] = src[tail + tid];
+        // halo after the x-slice: index loads, then gathers of whole rows
         const int hs = a.halo_start[p];
         const int hn = a.halo_start[p + 1] - hs;
+        XR* xsr = reinterpret_cast<XR*>(xs);
+        const XR* xr = reinterpret_cast<const XR*>(x);
         int hi[kHaloRegs];
 #pragma unroll
         for (int j = 0; j < kHaloRegs; ++j) {
             const int i = tid + j * nthr;
             if (i < hn) hi[j] = a.halo_idx[hs + i];
         }
-        X hv[kHaloRegs];
+        XR hv[kHaloRegs];
 #pragma unroll
         for (int j = 0; j < kHaloRegs; ++j) {
             const int i = tid + j * nthr;
-            if (i < hn) hv[j] = x[hi[j]];
+            if (i < hn) hv[j] = xr[hi[j]];
         }
 #pragma unroll
         for (int j = 0; j < kHaloRegs; ++j) {
             const int i = tid + j * nthr;
-            if (i < hn) xs[sz + i] = hv[j];
+            if (i < hn) xsr[sz + i] = hv[j];
         }
-        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr) xs[sz + i] = x[a.halo_idx[hs + i]];
+        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr) xsr[sz + i] = xr[a.halo_idx[hs + i]];
     }
     __syncthreads();  // counters initialised, x-slice and halo in LDS
 
@@ -261,37 +318,48 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
     const int ner = a.er_slice_start[p + 1] - e0;
     {
         const V* er_val = static_cast<const V*>(a.er_val);
-        int it = wave_fetch_add(&q_er, lane);
+        const XR* xr = reinterpret_cast<const XR*>(x);
+        int it = wave_fetch_add(&Q.q_er, lane);
         uint2 m = it < ner ? a.er_meta[e0 + it] : make_uint2(0, 0);
         while (it < ner) {
-            const int itn = wave_fetch_add(&q_er, lane);
+            const int itn = wave_fetch_add(&Q.q_er, lane);
             const uint2 mn = itn < ner ? a.er_meta[e0 + itn] : make_uint2(0, 0);
             const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
             const uint32_t steps = __builtin_amdgcn_readfirstlane(m.y);
             const V* ev = er_val + off + lane;
             const int32_t* ec = a.er_col + off + lane;
             const uint16_t lr = a.er_row[(size_t)(e0 + it) * C + r];
-            Acc acc = 0;
-            for (uint32_t t0 = 0; t0 < steps; t0 += kErChunk) {
-                int32_t c[kErChunk];
-                V v[kErChunk];
-                X xg[kErChunk];
+            Acc acc[NRHS];
 #pragma unroll
-                for (int j = 0; j < kErChunk; ++j)
+            for (int k = 0; k < NRHS; ++k) acc[k] = 0;
+            for (uint32_t t0 = 0; t0 < steps; t0 += kEr) {
+                int32_t c[kEr];
+                V v[kEr];
+                XR xg[kEr];
+#pragma unroll
+                for (int j = 0; j < kEr; ++j)
                     if (t0 + j < steps) {
                         c[j] = ec[(size_t)(t0 + j) * kWave];
                         v[j] = ev[(size_t)(t0 + j) * kWave];
                     }
 #pragma unroll
-                for (int j = 0; j < kErChunk; ++j)
-                    if (t0 + j < steps) xg[j] = x[c[j]];
+                for (int j = 0; j < kEr; ++j)
+                    if (t0 + j < steps) xg[j] = xr[c[j]];
 #pragma unroll
-                for (int j = 0; j < kErChunk; ++j)
-                    if (t0 + j < steps) acc = fma(P::value(v[j]), xg[j], acc);
+                for (int j = 0; j < kEr; ++j)
+                    if (t0 + j < steps) {
+                        const Acc vv = P::value(v[j]);
+#pragma unroll
+                        for (int k = 0; k < NRHS; ++k) acc[k] = fma(vv, (Acc)lane_of<X, NRHS>(xg[j], k), acc[k]);
+                    }
             }
-            acc = reduce_lanes<L>(acc);
-            if ((lane & (L - 1)) == 0 && lr != 0xFFFF) yer[lr] = acc;
-            wave_signal(&n_er_done, lane);
+#pragma unroll
+            for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<L>(acc[k]);
+            if ((lane & (L - 1)) == 0 && lr != 0xFFFF) {
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) yer[(size_t)lr * NRHS + k] = acc[k];
+            }
+            wave_signal(&Q.n_er_done, lane);
             it = itn;
             m = mn;
         }
@@ -299,14 +367,14 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
 
     // 3. ELL queue
     const V* ell_val = static_cast<const V*>(a.ell_val);
-    X* y = static_cast<X*>(a.y);
+    const XR* xsr = reinterpret_cast<const XR*>(xs);
     const int s0 = a.slice_start[p];
     const int ns = a.slice_start[p + 1] - s0;
     bool er_ready = ner == 0;
-    int item = wave_fetch_add(&q_ell, lane);
+    int item = wave_fetch_add(&Q.q_ell, lane);
     uint4 m = item < ns ? a.ell_meta[s0 + item] : make_uint4(0, 0, 0, 0);
     while (item < ns) {
-        const int nxt = wave_fetch_add(&q_ell, lane);
+        const int nxt = wave_fetch_add(&Q.q_ell, lane);
         // the next slice's metadata travels while this slice streams
         const uint4 mn = nxt < ns ? a.ell_meta[s0 + nxt] : make_uint4(0, 0, 0, 0);
         const uint4 mu = uniform4(m);
@@ -314,7 +382,9 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
         const int j0 = (int)(mu.y >> 16);
         const VL* v2 = reinterpret_cast<const VL*>(ell_val + mu.x) + lane;
         const CL* c2 = reinterpret_cast<const CL*>(a.ell_col + mu.x) + lane;
-        Acc acc = 0;
+        Acc acc[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) acc[k] = 0;
         for (uint32_t t0 = 0; t0 < steps; t0 += kEll) {
             VL v[kEll];
             CL c[kEll];
@@ -326,23 +396,89 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
                 }
 #pragma unroll
             for (int j = 0; j < kEll; ++j)
-                if (t0 + j < steps) P::step(v[j], c[j], xs, acc);
+                if (t0 + j < steps) {
+                    Acc val[KC];
+                    uint32_t col[KC];
+                    P::unpack(v[j], c[j], val, col);
+#pragma unroll
+                    for (int e = 0; e < KC; ++e) {
+                        const XR xv = xsr[col[e]];
+#pragma unroll
+                        for (int k = 0; k < NRHS; ++k)
+                            acc[k] = fma(val[e], (Acc)lane_of<X, NRHS>(xv, k), acc[k]);
+                    }
+                }
         }
-        acc = reduce_lanes<L>(acc);
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<L>(acc[k]);
         const uint64_t mask = ((uint64_t)mu.w << 32) | mu.z;
         if (mask != 0 && !er_ready) {
-            wave_wait(&n_er_done, ner);
+            wave_wait(&Q.n_er_done, ner);
             er_ready = true;
         }
         const int lr = j0 * C + r;
         if ((lane & (L - 1)) == 0 && lr < sz) {
-            if ((mask >> r) & 1u) acc += yer[lr];
-            y[ps + lr] = (X)acc;
+            if ((mask >> r) & 1u) {
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) acc[k] += yer[(size_t)lr * NRHS + k];
+            }
+            if constexpr (NRHS == 1) {
+                y[ps + lr] = (X)acc[0];
+            } else {
+                XR out;
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) out[k] = (X)acc[k];
+                reinterpret_cast<XR*>(y)[ps + lr] = out;
+            }
         }
         item = nxt;
         m = mn;
     }
-    (void)KC;
+}
+
+// y = A x: one workgroup per partition.
+template <int DT, int L>
+__global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
+    using X = typename Prec<DT>::X;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ Queues Q;
+    const int p = xcd_logical_id(blockIdx.x, gridDim.x);
+    process_partition<DT, L, 1>(a.m, p, static_cast<const X*>(a.x), static_cast<X*>(a.y), lds_raw, Q);
+}
+
+// Y_i = A_i X_i for a batch: persistent workgroups take (matrix, partition)
+// items from a global queue, largest first (the global queue of Alg. 3,
+// spread over matrices).  The last workgroup to leave resets the queue, so the
+// next launch (or graph replay) starts from zero.
+template <int DT, int L, int NRHS>
+__global__ void __launch_bounds__(1024) ehyb_spmm_batched_kernel(BatchArgs args) {
+    using X = typename Prec<DT>::X;
+    // Read the argument block in place (it is the first and only kernel
+    // argument): the per-matrix pointer tables are indexed at run time, which
+    // on a by-value copy would go through private memory.
+    const BatchArgs& a = *(const BatchArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+    (void)args;
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    __shared__ Queues Q;
+    __shared__ int s_item;
+    int32_t* counters = a.counters;
+    const int n_items = a.n_items;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= n_items) break;
+        const int2 w = a.items[it];
+        const int mi = __builtin_amdgcn_readfirstlane(w.x);
+        const int pi = __builtin_amdgcn_readfirstlane(w.y);
+        process_partition<DT, L, NRHS>(a.mats[mi], pi, static_cast<const X*>(a.X[mi]),
+                                       static_cast<X*>(a.Y[mi]), lds_raw, Q);
+        __syncthreads();  // LDS, Q and s_item are reused by the next item
+    }
+    if (threadIdx.x == 0 && atomicAdd(&counters[1], 1) == (int)gridDim.x - 1) {
+        __hip_atomic_store(&counters[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&counters[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 // Plain CSR SpMV: L lanes per row (rows of a wavefront are consecutive),
@@ -428,16 +564,21 @@ int launch_waves(const ehyb_plan& P) {
     return 16;
 }
 
+template <class K>
+void raise_lds_limit(K* kernel, size_t lds, bool& raised) {
+    if (!raised && lds > 64 * 1024) {
+        // allow the full 160 KiB of gfx950 LDS as dynamic shared memory
+        if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                160 * 1024 - kStaticLds) != hipSuccess)
+            (void)hipGetLastError();
+        raised = true;
+    }
+}
+
 template <int DT, int L>
 void launch_spmv(const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
-    static bool lds_raised = false;
-    if (!lds_raised && lds > 64 * 1024) {
-        // allow the full 160 KiB of gfx950 LDS as dynamic shared memory
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(&ehyb_spmv_kernel<DT, L>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024 - kStaticLds) != hipSuccess)
-            (void)hipGetLastError();
-        lds_raised = true;
-    }
+    static bool raised = false;
+    raise_lds_limit(&ehyb_spmv_kernel<DT, L>, lds, raised);
     hipLaunchKernelGGL((ehyb_spmv_kernel<DT, L>), dim3(nblocks), dim3(threads), lds, s, a);
 }
 
@@ -451,6 +592,34 @@ bool launch_spmv_dt(int L, const SpmvArgs& a, int nblocks, int threads, size_t l
         case 16: launch_spmv<DT, 16>(a, nblocks, threads, lds, s); return true;
         case 32: launch_spmv<DT, 32>(a, nblocks, threads, lds, s); return true;
         case 64: launch_spmv<DT, 64>(a, nblocks, threads, lds, s); return true;
+        default: return false;
+    }
+}
+
+template <int DT, int L, int NRHS>
+void launch_batched(const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+    static bool raised = false;
+    raise_lds_limit(&ehyb_spmm_batched_kernel<DT, L, NRHS>, lds, raised);
+    hipLaunchKernelGGL((ehyb_spmm_batched_kernel<DT, L, NRHS>), dim3(nblocks), dim3(threads), lds, s, a);
+}
+
+template <int DT, int NRHS>
+bool launch_batched_l(int L, const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+    switch (L) {
+        case 1: launch_batched<DT, 1, NRHS>(a, nblocks, threads, lds, s); return true;
+        case 4: launch_batched<DT, 4, NRHS>(a, nblocks, threads, lds, s); return true;
+        case 16: launch_batched<DT, 16, NRHS>(a, nblocks, threads, lds, s); return true;
+        default: return false;
+    }
+}
+
+template <int DT>
+bool launch_batched_dt(int L, int nrhs, const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+    switch (nrhs) {
+        case 1: return launch_batched_l<DT, 1>(L, a, nblocks, threads, lds, s);
+        case 2: return launch_batched_l<DT, 2>(L, a, nblocks, threads, lds, s);
+        case 4: return launch_batched_l<DT, 4>(L, a, nblocks, threads, lds, s);
+        case 8: return launch_batched_l<DT, 8>(L, a, nblocks, threads, lds, s);
         default: return false;
     }
 }
@@ -561,22 +730,9 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
         yout = (void*)(blob + Ly.yp);
     }
     SpmvArgs a;
-    a.part_start = (const int32_t*)(blob + Ly.part_start);
-    a.slice_start = (const int32_t*)(blob + Ly.slice_start);
-    a.er_slice_start = (const int32_t*)(blob + Ly.er_slice_start);
-    a.ell_free = (const int32_t*)(blob + Ly.ell_free);
-    a.halo_start = (const int32_t*)(blob + Ly.halo_start);
-    a.halo_idx = (const int32_t*)(blob + Ly.halo_idx);
-    a.ell_meta = (const uint4*)(blob + Ly.ell_meta);
-    a.er_meta = (const uint2*)(blob + Ly.er_meta);
-    a.er_row = (const uint16_t*)(blob + Ly.er_row);
-    a.ell_val = blob + Ly.ell_val;
-    a.ell_col = (const uint16_t*)(blob + Ly.ell_col);
-    a.er_val = blob + Ly.er_val;
-    a.er_col = (const int32_t*)(blob + Ly.er_col);
+    a.m = part_arrays(*P);
     a.x = xin;
     a.y = yout;
-    a.lds_rows = P->max_part_rows + P->max_halo;
     const int nblocks = P->nparts;
     const size_t lds = (size_t)lds_bytes_used(*P);
     if (lds > 160 * 1024 - kStaticLds) return fail(EHYB_EUNSUPPORTED, "partition and halo larger than the LDS budget");
@@ -595,6 +751,143 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     if (!(flags & EHYB_VEC_PERMUTED)) return ehyb_unpermute_y(P, yout, y, stream);
     return EHYB_OK;
 }
+
+ehyb_status ehyb_batch_create(const ehyb_plan* const* plans, int32_t n_plans, int32_t n_rhs, ehyb_batch** out) {
+    try {
+        if (!plans || !out) return fail(EHYB_EINVAL, "null argument");
+        *out = nullptr;
+        if (n_plans < 1 || n_plans > EHYB_BATCH_MAX) return fail(EHYB_EINVAL, "a batch holds 1 to 128 plans");
+        if (n_rhs != 1 && n_rhs != 2 && n_rhs != 4 && n_rhs != 8) return fail(EHYB_EINVAL, "n_rhs must be 1, 2, 4 or 8");
+        auto B = std::unique_ptr<ehyb_batch>(new ehyb_batch());
+        B->n_rhs = n_rhs;
+        for (int32_t i = 0; i < n_plans; ++i) {
+            const ehyb_plan* P = plans[i];
+            if (!P) return fail(EHYB_EINVAL, "null plan in batch");
+            if (i == 0) {
+                B->value_dtype = P->value_dtype;
+                B->L = P->L;
+            }
+            if (P->value_dtype != B->value_dtype || P->L != B->L)
+                return fail(EHYB_EINVAL, "batched plans must share value type and rows_per_wave");
+            if (P->n_rhs != n_rhs) return fail(EHYB_EINVAL, "plan was not built for this n_rhs");
+            B->plans.push_back(P);
+        }
+        if (B->L != 1 && B->L != 4 && B->L != 16)
+            return fail(EHYB_EUNSUPPORTED, "batched products support rows_per_wave 64, 16 or 4");
+        // work items, largest first: bytes each partition streams
+        struct Item {
+            int64_t cost;
+            int32_t m, p;
+        };
+        std::vector<Item> items;
+        for (int32_t i = 0; i < n_plans; ++i) {
+            const ehyb_plan& P = *B->plans[i];
+            for (int32_t p = 0; p < P.nparts; ++p) {
+                int64_t c = 0;
+                for (int32_t sl = P.slice_start[p]; sl < P.slice_start[p + 1]; ++sl)
+                    c += (int64_t)(P.ell_meta[4 * (size_t)sl + 1] & 0xFFFFu) * kWave * P.kc * (P.vbytes + 2);
+                for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e)
+                    c += (int64_t)P.er_meta[2 * (size_t)e + 1] * kWave * (P.vbytes + 4);
+                c += 2LL * (P.part_start[p + 1] - P.part_start[p]) * P.xbytes * n_rhs;
+                items.push_back({c, i, p});
+            }
+            B->lds_bytes = std::max<int64_t>(B->lds_bytes, lds_bytes_used(P, n_rhs));
+            B->algorithmic_bytes += algorithmic_bytes(P) + 2LL * (n_rhs - 1) * P.n * P.xbytes;
+        }
+        if (B->lds_bytes > 160 * 1024 - kStaticLds) return fail(EHYB_EINVAL, "a plan needs more LDS than a workgroup has");
+        std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+        B->items.reserve(items.size() * 2);
+        for (const Item& it : items) {
+            B->items.push_back(it.m);
+            B->items.push_back(it.p);
+        }
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            size_t at = off;
+            off += (bytes + kBlobAlign - 1) / kBlobAlign * kBlobAlign;
+            return at;
+        };
+        B->off_desc = take(sizeof(PartArrays) * (size_t)n_plans);
+        B->off_items = take(B->items.size() * 4);
+        B->off_counters = take(2 * sizeof(int32_t));
+        B->total = off;
+        *out = B.release();
+        return EHYB_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(EHYB_ENOMEM, "host allocation failed while building a batch");
+    }
+}
+
+ehyb_status ehyb_batch_device_bytes(const ehyb_batch* B, size_t* bytes) {
+    if (!B || !bytes) return fail(EHYB_EINVAL, "null argument");
+    *bytes = B->total;
+    return EHYB_OK;
+}
+
+ehyb_status ehyb_batch_upload(ehyb_batch* B, void* dev_blob, size_t bytes, void* stream) {
+    if (!B || !dev_blob) return fail(EHYB_EINVAL, "null argument");
+    if (bytes < B->total) return fail(EHYB_EINVAL, "device blob smaller than ehyb_batch_device_bytes");
+    if (!is_aligned(dev_blob, kBlobAlign)) return fail(EHYB_EINVAL, "device blob must be 256-byte aligned");
+    std::vector<PartArrays> desc;
+    for (const ehyb_plan* P : B->plans) {
+        if (!P->dev_blob) return fail(EHYB_ESTATE, "every plan of a batch must be uploaded first");
+        desc.push_back(part_arrays(*P));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    char* b = (char*)dev_blob;
+    const int32_t zeros[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(b + B->off_desc, desc.data(), desc.size() * sizeof(PartArrays),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B->items.empty())
+        e = hipMemcpyAsync(b + B->off_items, B->items.data(), B->items.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + B->off_counters, zeros, sizeof(zeros), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(EHYB_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
+    B->dev_blob = dev_blob;
+    return EHYB_OK;
+}
+
+ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* const* X, void* const* Y,
+                              uint32_t flags, void* stream) {
+    if (!B || !X || !Y) return fail(EHYB_EINVAL, "null argument");
+    if (!B->dev_blob) return fail(EHYB_ESTATE, "batch not uploaded");
+    if (n_rhs != B->n_rhs) return fail(EHYB_EINVAL, "n_rhs differs from the batch's");
+    if (flags != EHYB_VEC_PERMUTED) return fail(EHYB_EUNSUPPORTED, "batched products take permuted vectors only");
+    BatchArgs a;
+    std::memset(&a, 0, sizeof(a));
+    const char* b = (const char*)B->dev_blob;
+    a.mats = (const PartArrays*)(b + B->off_desc);
+    a.items = (const int2*)(b + B->off_items);
+    a.n_items = (int32_t)(B->items.size() / 2);
+    a.counters = (int32_t*)(b + B->off_counters);
+    const size_t eb = (B->value_dtype == EHYB_F64 ? 8 : 4);
+    for (size_t i = 0; i < B->plans.size(); ++i) {
+        if (!X[i] || !Y[i]) return fail(EHYB_EINVAL, "null vector in batch");
+        if (!is_aligned(X[i], eb * n_rhs) || !is_aligned(Y[i], eb * n_rhs))
+            return fail(EHYB_EINVAL, "batched vectors must be aligned to a whole row (n_rhs elements)");
+        const size_t vb = (size_t)B->plans[i]->n * eb * n_rhs;
+        const char* xi = (const char*)X[i];
+        const char* yi = (const char*)Y[i];
+        if (xi < yi + vb && yi < xi + vb) return fail(EHYB_EINVAL, "X and Y of a matrix must not overlap");
+        a.X[i] = X[i];
+        a.Y[i] = Y[i];
+    }
+    if (a.n_items == 0) return EHYB_OK;
+    const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024 - kStaticLds) / std::max<int64_t>(1, B->lds_bytes)));
+    const int nblocks = std::min(a.n_items, 256 * per_cu);
+    bool ok = false;
+    hipStream_t s = (hipStream_t)stream;
+    switch (B->value_dtype) {
+        case EHYB_F64: ok = launch_batched_dt<EHYB_F64>(B->L, n_rhs, a, nblocks, 1024, (size_t)B->lds_bytes, s); break;
+        case EHYB_F32: ok = launch_batched_dt<EHYB_F32>(B->L, n_rhs, a, nblocks, 1024, (size_t)B->lds_bytes, s); break;
+        case EHYB_BF16: ok = launch_batched_dt<EHYB_BF16>(B->L, n_rhs, a, nblocks, 1024, (size_t)B->lds_bytes, s); break;
+        default: break;
+    }
+    if (!ok) return fail(EHYB_EUNSUPPORTED, "no batched kernel for this value type, rows_per_wave and n_rhs");
+    return launch_status("ehyb_spmm_batched");
+}
+
+void ehyb_batch_destroy(ehyb_batch* B) { delete B; }
 
 ehyb_status ehyb_csr_spmv_f64(int64_t n_rows, int64_t nnz, const int32_t* row_ptr, const int32_t* col_idx,
                               const double* val, const double* x, double* y, int32_t lanes_per_row,

@@ -249,11 +249,11 @@ BlobLayout compute_layout(const ehyb_plan& p) {
     return L;
 }
 
-// LDS of one ehyb_spmv workgroup: x-slice + halo, then one residual
-// accumulator per row when the plan has residual entries.
-int64_t lds_bytes_used(const ehyb_plan& p) {
+// LDS of one workgroup: x-slice + halo, then one residual accumulator per
+// row when the plan has residual entries, each n_rhs elements wide.
+int64_t lds_bytes_used(const ehyb_plan& p, int n_rhs) {
     const int64_t rows = (int64_t)p.max_part_rows + p.max_halo + (p.ner_slices > 0 ? p.max_part_rows : 0);
-    return rows * p.xbytes;
+    return rows * p.xbytes * n_rhs;
 }
 
 // Residual position of every permuted row (e*C + r, or -1), from er_row.
@@ -581,6 +581,10 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
         Error e = validate(A);
         if (!e.ok()) return fail(e.status, e.msg);
         if (prm.halo_rows < -1) return fail(EHYB_EINVAL, "halo_rows must be >= -1");
+        if (prm.reserved != 0) return fail(EHYB_EINVAL, "reserved parameter field must be 0");
+        if (prm.n_rhs == 0) prm.n_rhs = 1;
+        if (prm.n_rhs != 1 && prm.n_rhs != 2 && prm.n_rhs != 4 && prm.n_rhs != 8)
+            return fail(EHYB_EINVAL, "n_rhs must be 1, 2, 4 or 8");
         if (prm.value_dtype < 0 || prm.value_dtype > 2) return fail(EHYB_EINVAL, "unknown value dtype");
         if (prm.rows_per_wave == 0) prm.rows_per_wave = kWave;
         if (prm.rows_per_wave < 1 || prm.rows_per_wave > kWave ||
@@ -608,8 +612,9 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
         P->C = prm.rows_per_wave;
         P->L = kWave / prm.rows_per_wave;
         P->kc = kc_for(prm.value_dtype);
-        // LDS per partition row: its x element and its residual accumulator
-        const int64_t tau = 2 * (int64_t)P->xbytes;
+        // LDS per partition row: its x elements and its residual accumulators
+        P->n_rhs = prm.n_rhs;
+        const int64_t tau = 2 * (int64_t)P->xbytes * prm.n_rhs;
         const int64_t max_rows = std::min<int64_t>(65535, (prm.lds_bytes - kStaticLds) / tau);
         if (max_rows < 1) return fail(EHYB_EINVAL, "lds_bytes smaller than one partition row");
         // Eq. 1-2: smallest K with n*tau/(K*P) < SHM, VecSize = ceil(n/(K*P))
@@ -654,7 +659,7 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
                 for (int64_t i = 0; i < n; ++i) sizes[part[i]]++;
                 for (int32_t s2 : sizes) maxp = std::max(maxp, s2);
             }
-            const int64_t room = (int64_t)(prm.lds_bytes - kStaticLds) / P->xbytes - 2 * (int64_t)maxp;
+            const int64_t room = (int64_t)(prm.lds_bytes - kStaticLds) / ((int64_t)P->xbytes * prm.n_rhs) - 2 * (int64_t)maxp;
             halo_cap = (int32_t)std::max<int64_t>(0, std::min<int64_t>(room, 65535 - (int64_t)maxp));
             if (prm.halo_rows > 0) halo_cap = std::min(halo_cap, prm.halo_rows);
         }
@@ -683,6 +688,7 @@ ehyb_status ehyb_plan_stats_get(const ehyb_plan* P, ehyb_plan_stats* out) {
     out->n_halo = (int64_t)P->halo_idx.size();
     out->max_halo = P->max_halo;
     out->lds_bytes_used = (int32_t)lds_bytes_used(*P);
+    out->n_rhs = P->n_rhs;
     out->device_bytes = (int64_t)compute_layout(*P).total;
     out->algorithmic_bytes = algorithmic_bytes(*P);
     out->nparts = P->nparts;
@@ -791,13 +797,13 @@ void ehyb_plan_destroy(ehyb_plan* P) { delete P; }
 }  // extern "C"
 
 // ------------------------------------------------------------- plan files
-// Layout: magic "EHYBPLN4", u32 version, then fixed header fields and arrays
+// Layout: magic "EHYBPLN5", u32 version, then fixed header fields and arrays
 // (each prefixed by its u64 byte length), then a u64 FNV-1a checksum of all
 // preceding bytes.
 
 namespace {
-const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '4'};
-const uint32_t kVersion = 4;
+const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '5'};
+const uint32_t kVersion = 5;
 
 uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
     for (size_t i = 0; i < n; ++i) {
@@ -879,8 +885,8 @@ const char* validate_loaded(const ehyb_plan& P) {
         }
     }
     if (maxh != P.max_halo) return "plan file largest halo is inconsistent";
-    if (lds_bytes_used(P) > 160 * 1024 - kStaticLds) return "plan file needs more LDS than a workgroup has";
-    const int64_t max_rows = std::min<int64_t>(65535, (int64_t)(160 * 1024 - kStaticLds) / (2 * P.xbytes));
+    if (lds_bytes_used(P, P.n_rhs) > 160 * 1024 - kStaticLds) return "plan file needs more LDS than a workgroup has";
+    const int64_t max_rows = std::min<int64_t>(65535, (int64_t)(160 * 1024 - kStaticLds) / (2 * P.xbytes * P.n_rhs));
     for (int32_t p = 0; p < P.nparts; ++p) {
         const int64_t sz = (int64_t)P.part_start[p + 1] - P.part_start[p];
         const int64_t sl = (int64_t)P.slice_start[p + 1] - P.slice_start[p];
@@ -1027,6 +1033,9 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
             return fail(EHYB_EINVAL, "plan file header is inconsistent");
         P->vbytes = P->value_dtype == EHYB_F64 ? 8 : (P->value_dtype == EHYB_F32 ? 4 : 2);
         P->xbytes = P->value_dtype == EHYB_F64 ? 8 : 4;
+        P->n_rhs = P->params.n_rhs;
+        if (P->n_rhs != 1 && P->n_rhs != 2 && P->n_rhs != 4 && P->n_rhs != 8)
+            return fail(EHYB_EINVAL, "plan file right-hand side count is invalid");
         const uint64_t lim = (uint64_t)buf.size();
         r.vec(P->perm, lim);
         r.vec(P->part_start, lim);

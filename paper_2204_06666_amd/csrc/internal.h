@@ -81,11 +81,23 @@ struct ehyb_plan {
     int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0, nnz_halo = 0;
     int32_t max_halo = 0;
     double t_graph = 0, t_partition = 0, t_reorder = 0, t_encode = 0;
+    int32_t n_rhs = 1;             // right-hand sides the LDS budget is sized for
     int32_t launch_waves = 0;      // 0 = automatic launch shape
     // device binding (non-owning)
     void* dev_blob = nullptr;
     size_t dev_bytes = 0;
     ehyb::BlobLayout layout;
+};
+
+// A batch of plans for ehyb_spmm_batched (host side).
+struct ehyb_batch {
+    std::vector<const ehyb_plan*> plans;
+    int32_t n_rhs = 1, value_dtype = EHYB_F64, L = 1;
+    std::vector<int32_t> items;      // (matrix, partition) pairs, largest first
+    size_t off_desc = 0, off_items = 0, off_counters = 0, total = 0;
+    void* dev_blob = nullptr;
+    int64_t lds_bytes = 0;           // dynamic LDS of one workgroup
+    int64_t algorithmic_bytes = 0;   // sum over matrices, n_rhs-wide x and y
 };
 
 namespace ehyb {
@@ -94,5 +106,5 @@ ehyb_status fail(ehyb_status st, const std::string& msg);
 ehyb_status ok();
 BlobLayout compute_layout(const ehyb_plan& p);
 int64_t algorithmic_bytes(const ehyb_plan& p);
-int64_t lds_bytes_used(const ehyb_plan& p);
+int64_t lds_bytes_used(const ehyb_plan& p, int n_rhs = 1);
 }  // namespace ehyb

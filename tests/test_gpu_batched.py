@@ -1,0 +1,110 @@
+"""GPU parity of the batched multi-matrix, multi-RHS product (one persistent
+launch), including repeated launches and HIP graph replays."""
+import numpy as np
+import pytest
+
+import matgen
+import oracle
+from oracle.precision import gamma32, quantize
+from paper_2204_06666_amd import EHYB_BF16, EHYB_F32, EHYB_F64, Batch, Plan
+
+pytestmark = pytest.mark.gpu
+
+import torch  # noqa: E402
+
+
+def _mats():
+    return [matgen.stencil3d(14, perm_seed=1, val_seed=2),
+            matgen.knn_fem(900, perm_seed=3, pt_seed=4, val_seed=5),
+            matgen.config_matrix(1),
+            matgen.powerlaw(6000, exponent=2.3, mean_deg=8, seed=6),
+            matgen.random_small(150, 0.05, 7, empty_rows=10, dense_row=True),
+            matgen.stencil3d(9, points=7, val_seed=8)]
+
+
+def _check(A, X, Y, dt, what):
+    m = np.diff(A.row_ptr)
+    name = {EHYB_F64: "f64", EHYB_F32: "f32", EHYB_BF16: "bf16"}[dt]
+    Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, name))
+    Xq = X.astype(np.float64) if dt == EHYB_F64 else X.astype(np.float32).astype(np.float64)
+    ref = oracle.spmm(Aq, Xq)
+    Aabs = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, np.abs(Aq.val))
+    s = oracle.spmm(Aabs, np.abs(Xq))
+    tol = 1e-12 if dt == EHYB_F64 else gamma32(m + 2)[:, None]
+    err = np.abs(Y - ref)
+    ok = (err <= tol * s) | ((s == 0) & (Y == ref))
+    assert ok.all(), f"{what}: max err {err[~ok].max():.3e}"
+
+
+def _run(dt, n_rhs, rpw=64, halo=0):
+    mats = _mats()
+    # about three partitions per matrix, within the LDS budget of n_rhs-wide rows
+    cap = (160 * 1024 - 64) // (2 * (8 if dt == EHYB_F64 else 4) * n_rhs)
+    plans = [Plan(A, value_dtype=dt, n_rhs=n_rhs, rows_per_wave=rpw, halo_rows=halo,
+                  slice_rows=max(64, min(A.n_rows // 3, cap))).upload("cuda:0") for A in mats]
+    g = matgen.rng(11)
+    X = [g.uniform(-1, 1, (A.n_rows, n_rhs)) for A in mats]
+    tdt = torch.float64 if dt == EHYB_F64 else torch.float32
+    Xd = [torch.from_numpy(x[p.perm()]).to("cuda:0", tdt).contiguous() for x, p in zip(X, plans)]
+    Yd = [torch.empty_like(x) for x in Xd]
+    B = Batch(plans, n_rhs)
+    B.spmm(Xd, Yd)
+    torch.cuda.synchronize()
+    return mats, plans, X, Xd, Yd, B
+
+
+def _unperm(p, Yp):
+    Y = np.empty_like(Yp)
+    Y[p.perm()] = Yp
+    return Y
+
+
+@pytest.mark.parametrize("dt,n_rhs", [(EHYB_F32, 8), (EHYB_F32, 1), (EHYB_F32, 4), (EHYB_F64, 2),
+                                      (EHYB_F64, 8), (EHYB_BF16, 8), (EHYB_BF16, 2)])
+@pytest.mark.parametrize("rpw,halo", [(64, 0), (16, -1)])
+def test_batched_parity(dt, n_rhs, rpw, halo):
+    mats, plans, X, Xd, Yd, B = _run(dt, n_rhs, rpw, halo)
+    for A, p, x, y in zip(mats, plans, X, Yd):
+        Y = _unperm(p, y.cpu().numpy().astype(np.float64))
+        _check(A, x, Y, dt, f"dt={dt} n_rhs={n_rhs} rpw={rpw} halo={halo} n={A.n_rows}")
+    print(f"[batched] dt={dt} n_rhs={n_rhs} rpw={rpw} halo={halo} ok", flush=True)
+
+
+def test_repeated_launches_identical():
+    mats, plans, X, Xd, Yd, B = _run(EHYB_F32, 8)
+    first = [y.clone() for y in Yd]
+    for _ in range(5):
+        B.spmm(Xd, Yd)
+        for a, b in zip(first, Yd):
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32))
+
+
+def test_graph_capture_replays():
+    """One launch recorded in a HIP graph; replayed with new inputs between
+    replays and eager work in between, each replay checked against an eager
+    launch on the same inputs."""
+    mats, plans, X, Xd, Yd, B = _run(EHYB_F32, 8)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        B.spmm(Xd, Yd)        # warm up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        B.spmm(Xd, Yd, stream=s)
+    rng = matgen.rng(99)
+    Ye = [torch.empty_like(y) for y in Yd]
+    for rep in range(4):
+        for x in Xd:
+            x.copy_(torch.from_numpy(rng.uniform(-1, 1, tuple(x.shape))).to(x))
+        g.replay()
+        torch.cuda.synchronize()
+        B.spmm(Xd, Ye)       # eager reference launch between replays
+        torch.cuda.synchronize()
+        for a, b in zip(Yd, Ye):
+            assert torch.equal(a.view(torch.int32), b.view(torch.int32)), f"replay {rep}"
+    for A, p, x, y in zip(mats, plans, Xd, Yd):
+        Xh = np.empty(tuple(x.shape))
+        Xh[p.perm()] = x.cpu().numpy()
+        _check(A, Xh, _unperm(p, y.cpu().numpy().astype(np.float64)), EHYB_F32, "after replays")
