@@ -142,15 +142,22 @@ Error validate(const ehyb_csr_host* A) {
 Graph build_graph(const ehyb_csr_host* A) {
     const int32_t n = (int32_t)A->n_rows;
     const int64_t nnz = A->nnz;
-    // transpose pattern (CSC): rows of each column, ascending
+    // transpose pattern (CSC): rows of each column, ascending.  Counts and
+    // slots are claimed with atomic adds, then each column is sorted, so the
+    // result does not depend on the thread schedule.
     std::vector<int64_t> tptr(n + 1, 0);
-    for (int64_t p = 0; p < nnz; ++p) tptr[A->col_idx[p] + 1]++;
+#pragma omp parallel for schedule(static)
+    for (int64_t p = 0; p < nnz; ++p) __atomic_fetch_add(&tptr[A->col_idx[p] + 1], 1, __ATOMIC_RELAXED);
     for (int32_t j = 0; j < n; ++j) tptr[j + 1] += tptr[j];
-    std::vector<int32_t> trow(nnz);
+    uvec<int32_t> trow(nnz);
     {
         std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+#pragma omp parallel for schedule(dynamic, 4096)
         for (int32_t i = 0; i < n; ++i)
-            for (int64_t p = A->row_ptr[i]; p < A->row_ptr[i + 1]; ++p) trow[fill[A->col_idx[p]]++] = i;
+            for (int64_t p = A->row_ptr[i]; p < A->row_ptr[i + 1]; ++p)
+                trow[__atomic_fetch_add(&fill[A->col_idx[p]], 1, __ATOMIC_RELAXED)] = i;
+#pragma omp parallel for schedule(dynamic, 4096)
+        for (int32_t j = 0; j < n; ++j) std::sort(trow.begin() + tptr[j], trow.begin() + tptr[j + 1]);
     }
     Graph g;
     g.n = n;

@@ -3,7 +3,10 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "ehyb.h"
@@ -16,13 +19,36 @@ constexpr int kc_for(int value_dtype) { return value_dtype == EHYB_F64 ? 2 : (va
 constexpr size_t kBlobAlign = 256;
 constexpr int kStaticLds = 64;         // LDS the SpMV kernel keeps for its queue counters
 
+// Allocator whose resize() leaves new elements uninitialised, so that large
+// arrays filled by parallel loops are not first zeroed by one thread.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+    template <class U>
+    void construct(U* p) noexcept {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... Args>
+    void construct(U* p, Args&&... args) {
+        ::new ((void*)p) U(std::forward<Args>(args)...);
+    }
+};
+template <class T>
+using uvec = std::vector<T, NoInitAlloc<T>>;
+
 // Undirected graph in CSR form with vertex and edge weights.
 struct Graph {
     int32_t n = 0;
-    std::vector<int64_t> xadj;   // [n+1]
-    std::vector<int32_t> adj;    // [xadj[n]]
-    std::vector<int32_t> ew;     // edge weights, parallel to adj
-    std::vector<int32_t> vw;     // vertex weights [n]
+    uvec<int64_t> xadj;   // [n+1]
+    uvec<int32_t> adj;    // [xadj[n]]
+    uvec<int32_t> ew;     // edge weights, parallel to adj
+    uvec<int32_t> vw;     // vertex weights [n]
     int64_t total_vw() const;
 };
 

@@ -13,6 +13,17 @@
 // Edge weights count stored entries: an undirected edge {i, j} weighs 1 if
 // only one of a_ij, a_ji is stored and 2 if both are, so the weight of the
 // cut equals the number of entries that land in the residual part.
+//
+// The paper's partitioner is multi-threaded and its reordering is named as the
+// preprocessing bottleneck (Section 4); here every phase over the whole graph
+// runs on all host threads: matching, contraction, k-way refinement, and the
+// two halves of every bisection.  Each parallel step is written so that the
+// result depends on the seed only, never on the number of threads or their
+// timing: matching pairs vertices that choose each other, refinement computes
+// moves from a snapshot and accepts them in a fixed order, and every node of
+// the bisection tree draws from its own random stream.
+#include <omp.h>
+
 #include <algorithm>
 #include <cstring>
 #include <numeric>
@@ -45,6 +56,15 @@ struct Rng {
     }
 };
 
+// Stateless 64-bit mix (the splitmix64 finaliser) for per-vertex tie-breaks and
+// per-task seeds.
+inline uint64_t mix64(uint64_t z) {
+    z += 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
 std::vector<int32_t> random_order(int32_t n, Rng& rng) {
     std::vector<int32_t> p(n);
     std::iota(p.begin(), p.end(), 0);
@@ -53,30 +73,61 @@ std::vector<int32_t> random_order(int32_t n, Rng& rng) {
 }
 
 // ---------------------------------------------------------------- coarsening
-// Heavy-edge matching: visit vertices in random order, pair each unmatched
-// vertex with the unmatched neighbour joined by the heaviest edge (lighter
-// partner on ties) as long as the pair stays under maxvw.
-Graph coarsen(const Graph& g, int32_t maxvw, Rng& rng, std::vector<int32_t>& cmap) {
+// Heavy-edge matching in rounds: every unmatched vertex picks the unmatched
+// neighbour joined by the heaviest edge (then the lighter one, then a seeded
+// per-vertex hash) whose combined weight stays under maxvw; two vertices that
+// picked each other are matched.  A final pass in vertex order pairs what is
+// left greedily.  Then the matched pairs are contracted; a coarse vertex's
+// edges keep the order in which they are first met.
+Graph coarsen(const Graph& g, int32_t maxvw, uint64_t key, std::vector<int32_t>& cmap) {
     const int32_t n = g.n;
-    std::vector<int32_t> match(n, -1);
-    for (int32_t v : random_order(n, rng)) {
-        if (match[v] != -1) continue;
-        int32_t best = -1, bestw = -1, bestvw = 0;
-        for (int64_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
-            int32_t u = g.adj[e];
-            if (match[u] != -1 || u == v || g.vw[v] + g.vw[u] > maxvw) continue;
-            if (g.ew[e] > bestw || (g.ew[e] == bestw && g.vw[u] < bestvw)) {
-                best = u;
-                bestw = g.ew[e];
-                bestvw = g.vw[u];
+    std::vector<int32_t> match(n, -1), pref(n, -1);
+    auto better = [&](int32_t u, int32_t w, int32_t best, int32_t bestw) {
+        if (best < 0 || w > bestw) return true;
+        if (w < bestw) return false;
+        if (g.vw[u] != g.vw[best]) return g.vw[u] < g.vw[best];
+        return mix64(key ^ (uint64_t)u) > mix64(key ^ (uint64_t)best);
+    };
+    for (int round = 0; round < 4; ++round) {
+        int64_t matched = 0;
+#pragma omp parallel for schedule(dynamic, 4096)
+        for (int32_t v = 0; v < n; ++v) {
+            int32_t best = -1, bestw = -1;
+            if (match[v] == -1) {
+                for (int64_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
+                    const int32_t u = g.adj[e];
+                    if (match[u] != -1 || u == v || g.vw[v] + g.vw[u] > maxvw) continue;
+                    if (better(u, g.ew[e], best, bestw)) {
+                        best = u;
+                        bestw = g.ew[e];
+                    }
+                }
+            }
+            pref[v] = best;
+        }
+#pragma omp parallel for schedule(static) reduction(+ : matched)
+        for (int32_t v = 0; v < n; ++v) {
+            const int32_t u = pref[v];
+            if (u >= 0 && pref[u] == v) {
+                match[v] = u;
+                ++matched;
             }
         }
-        if (best >= 0) {
-            match[v] = best;
-            match[best] = v;
-        } else {
-            match[v] = v;
+        if (matched * 50 < n) break;
+    }
+    for (int32_t v = 0; v < n; ++v) {
+        if (match[v] != -1) continue;
+        int32_t best = -1, bestw = -1;
+        for (int64_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
+            const int32_t u = g.adj[e];
+            if (match[u] != -1 || u == v || g.vw[v] + g.vw[u] > maxvw) continue;
+            if (better(u, g.ew[e], best, bestw)) {
+                best = u;
+                bestw = g.ew[e];
+            }
         }
+        match[v] = best >= 0 ? best : v;
+        if (best >= 0) match[best] = v;
     }
     cmap.assign(n, -1);
     std::vector<int32_t> rep;
@@ -90,32 +141,52 @@ Graph coarsen(const Graph& g, int32_t maxvw, Rng& rng, std::vector<int32_t>& cma
             ++nc;
         }
     }
+    // contraction: each coarse vertex writes into a slot range sized by the
+    // degrees of its two members, then the ranges are packed
+    std::vector<int64_t> ub(nc + 1, 0);
+    for (int32_t ci = 0; ci < nc; ++ci) {
+        const int32_t v = rep[ci], u = match[v];
+        ub[ci + 1] = ub[ci] + (g.xadj[v + 1] - g.xadj[v]) + (u != v ? g.xadj[u + 1] - g.xadj[u] : 0);
+    }
+    uvec<int32_t> tadj(ub[nc]), tew(ub[nc]), cnt(nc);
     Graph c;
     c.n = nc;
-    c.xadj.assign(nc + 1, 0);
     c.vw.assign(nc, 0);
-    c.adj.reserve(g.adj.size() / 2 + 16);
-    c.ew.reserve(g.adj.size() / 2 + 16);
-    std::vector<int64_t> marker(nc, -1);
-    for (int32_t ci = 0; ci < nc; ++ci) {
-        const int64_t start = (int64_t)c.adj.size();
-        const int32_t v = rep[ci], u = match[v];
-        c.vw[ci] = g.vw[v] + (u != v ? g.vw[u] : 0);
-        for (int k = 0; k < (u != v ? 2 : 1); ++k) {
-            const int32_t w = k == 0 ? v : u;
-            for (int64_t e = g.xadj[w]; e < g.xadj[w + 1]; ++e) {
-                const int32_t cu = cmap[g.adj[e]];
-                if (cu == ci) continue;
-                if (marker[cu] >= start) {
-                    c.ew[marker[cu]] += g.ew[e];
-                } else {
-                    marker[cu] = (int64_t)c.adj.size();
-                    c.adj.push_back(cu);
-                    c.ew.push_back(g.ew[e]);
+#pragma omp parallel
+    {
+        std::vector<int64_t> marker(nc, -1);
+#pragma omp for schedule(dynamic, 1024)
+        for (int32_t ci = 0; ci < nc; ++ci) {
+            const int64_t start = ub[ci];
+            int64_t end = start;
+            const int32_t v = rep[ci], u = match[v];
+            c.vw[ci] = g.vw[v] + (u != v ? g.vw[u] : 0);
+            for (int k = 0; k < (u != v ? 2 : 1); ++k) {
+                const int32_t w = k == 0 ? v : u;
+                for (int64_t e = g.xadj[w]; e < g.xadj[w + 1]; ++e) {
+                    const int32_t cu = cmap[g.adj[e]];
+                    if (cu == ci) continue;
+                    if (marker[cu] >= start) {
+                        tew[marker[cu]] += g.ew[e];
+                    } else {
+                        marker[cu] = end;
+                        tadj[end] = cu;
+                        tew[end] = g.ew[e];
+                        ++end;
+                    }
                 }
             }
+            cnt[ci] = (int32_t)(end - start);
         }
-        c.xadj[ci + 1] = (int64_t)c.adj.size();
+    }
+    c.xadj.assign(nc + 1, 0);
+    for (int32_t ci = 0; ci < nc; ++ci) c.xadj[ci + 1] = c.xadj[ci] + cnt[ci];
+    c.adj.resize(c.xadj[nc]);
+    c.ew.resize(c.xadj[nc]);
+#pragma omp parallel for schedule(dynamic, 4096)
+    for (int32_t ci = 0; ci < nc; ++ci) {
+        std::copy(tadj.begin() + ub[ci], tadj.begin() + ub[ci] + cnt[ci], c.adj.begin() + c.xadj[ci]);
+        std::copy(tew.begin() + ub[ci], tew.begin() + ub[ci] + cnt[ci], c.ew.begin() + c.xadj[ci]);
     }
     return c;
 }
@@ -248,72 +319,88 @@ void fm_2way(const Graph& g, std::vector<int8_t>& side, int64_t lo, int64_t hi, 
 }
 
 // Greedy graph growing from a random seed, then FM; best of several trials.
+// The trials run as separate tasks, each with its own generator drawn from
+// `rng`; ties between trials go to the lower trial index.
+void grow_and_refine(const Graph& g, int64_t target0, int64_t lo, int64_t hi, Rng& rng,
+                     std::vector<int8_t>& side) {
+    const int32_t n = g.n;
+    side.assign(n, 1);
+    std::vector<int64_t> gain(n, 0);
+    std::priority_queue<HeapItem> q;
+    int64_t w0 = 0;
+    int32_t scan = (int32_t)rng.below((uint32_t)n);
+    while (w0 < target0) {
+        int32_t v = -1;
+        while (!q.empty()) {
+            HeapItem it = q.top();
+            q.pop();
+            if (side[it.v] == 1 && it.gain == gain[it.v]) {
+                v = it.v;
+                break;
+            }
+        }
+        if (v < 0) {  // new component or first seed
+            for (int32_t k = 0; k < n; ++k) {
+                const int32_t c = (scan + k) % n;
+                if (side[c] == 1) {
+                    v = c;
+                    scan = c;
+                    break;
+                }
+            }
+            if (v < 0) break;
+        }
+        if (w0 + g.vw[v] > hi && w0 >= lo) break;
+        side[v] = 0;
+        w0 += g.vw[v];
+        for (int64_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
+            const int32_t u = g.adj[e];
+            if (side[u] == 1) {
+                gain[u] += 2 * (int64_t)g.ew[e];
+                q.push({gain[u], u});
+            }
+        }
+    }
+    fm_2way(g, side, lo, hi, rng);
+}
+
 void bisect(const Graph& g, int64_t target0, int64_t lo, int64_t hi, Rng& rng,
             std::vector<int8_t>& best_side) {
     const int32_t n = g.n;
     const int trials = n > 20000 ? 3 : 6;
-    int64_t best_cut = -1, best_dev = 0;
-    std::vector<int8_t> side(n);
-    std::vector<int64_t> gain(n);
+    std::vector<uint64_t> seeds(trials);
+    for (auto& s : seeds) s = rng.next();
+    std::vector<std::vector<int8_t>> sides(trials);
+    std::vector<int64_t> cut(trials), dev(trials);
     for (int t = 0; t < trials; ++t) {
-        std::fill(side.begin(), side.end(), 1);
-        std::fill(gain.begin(), gain.end(), 0);
-        std::priority_queue<HeapItem> q;
-        int64_t w0 = 0;
-        int32_t scan = (int32_t)rng.below((uint32_t)n);
-        while (w0 < target0) {
-            int32_t v = -1;
-            while (!q.empty()) {
-                HeapItem it = q.top();
-                q.pop();
-                if (side[it.v] == 1 && it.gain == gain[it.v]) {
-                    v = it.v;
-                    break;
-                }
-            }
-            if (v < 0) {  // new component or first seed
-                for (int32_t k = 0; k < n; ++k) {
-                    const int32_t c = (scan + k) % n;
-                    if (side[c] == 1) {
-                        v = c;
-                        scan = c;
-                        break;
-                    }
-                }
-                if (v < 0) break;
-            }
-            if (w0 + g.vw[v] > hi && w0 >= lo) break;
-            side[v] = 0;
-            w0 += g.vw[v];
-            for (int64_t e = g.xadj[v]; e < g.xadj[v + 1]; ++e) {
-                const int32_t u = g.adj[e];
-                if (side[u] == 1) {
-                    gain[u] += 2 * (int64_t)g.ew[e];
-                    q.push({gain[u], u});
-                }
-            }
-        }
-        fm_2way(g, side, lo, hi, rng);
-        int64_t wz = 0;
-        for (int32_t v = 0; v < n; ++v)
-            if (side[v] == 0) wz += g.vw[v];
-        const int64_t dev = wz < lo ? lo - wz : (wz > hi ? wz - hi : 0);
-        const int64_t cut = cut_2way(g, side);
-        if (best_cut < 0 || dev < best_dev || (dev == best_dev && cut < best_cut)) {
-            best_cut = cut;
-            best_dev = dev;
-            best_side = side;
+#pragma omp task default(shared) firstprivate(t) if (g.xadj[n] > 20000)
+        {
+            Rng r(seeds[t]);
+            grow_and_refine(g, target0, lo, hi, r, sides[t]);
+            int64_t wz = 0;
+            for (int32_t v = 0; v < n; ++v)
+                if (sides[t][v] == 0) wz += g.vw[v];
+            dev[t] = wz < lo ? lo - wz : (wz > hi ? wz - hi : 0);
+            cut[t] = cut_2way(g, sides[t]);
         }
     }
+#pragma omp taskwait
+    int best = 0;
+    for (int t = 1; t < trials; ++t)
+        if (dev[t] < dev[best] || (dev[t] == dev[best] && cut[t] < cut[best])) best = t;
+    best_side.swap(sides[best]);
 }
 
 // Recursive bisection of g into parts [p0, p0 + k); writes part[ids[v]].
+// Each node of the bisection tree seeds its own generator from (key, p0, k),
+// and the two halves run as separate tasks.
 void recursive_bisection(const Graph& g, const std::vector<int32_t>& ids, int32_t p0, int32_t k,
-                         Rng& rng, std::vector<int32_t>& part) {
+                         uint64_t key, std::vector<int32_t>& part) {
     if (k == 1 || g.n == 0) {
         for (int32_t v = 0; v < g.n; ++v) part[ids[v]] = p0;
         return;
     }
+    Rng rng(mix64(key ^ mix64(((uint64_t)(uint32_t)p0 << 32) | (uint32_t)k)));
     const int32_t k1 = k / 2;
     const int64_t W = g.total_vw();
     const int64_t target0 = (W * k1 + k / 2) / k;
@@ -323,11 +410,15 @@ void recursive_bisection(const Graph& g, const std::vector<int32_t>& ids, int32_
     std::vector<int8_t> side;
     bisect(g, target0, std::max<int64_t>(0, target0 - delta), target0 + delta, rng, side);
     for (int8_t s = 0; s < 2; ++s) {
-        std::vector<int32_t> loc_ids;
-        Graph sub = induced(g, side, s, loc_ids);
-        for (auto& v : loc_ids) v = ids[v];
-        recursive_bisection(sub, loc_ids, s == 0 ? p0 : p0 + k1, s == 0 ? k1 : k - k1, rng, part);
+#pragma omp task default(shared) firstprivate(s) if (g.n > 512)
+        {
+            std::vector<int32_t> loc_ids;
+            Graph sub = induced(g, side, s, loc_ids);
+            for (auto& v : loc_ids) v = ids[v];
+            recursive_bisection(sub, loc_ids, s == 0 ? p0 : p0 + k1, s == 0 ? k1 : k - k1, key, part);
+        }
     }
+#pragma omp taskwait
 }
 
 // Connectivity of v to the parts around it: returns own-part weight (ID),
@@ -349,37 +440,77 @@ inline int64_t connectivity(const Graph& g, const std::vector<int32_t>& part, in
     return id;
 }
 
-// Greedy k-way boundary refinement under the hard cap.
+// Greedy k-way boundary refinement under the hard cap, in parallel.  A pass
+// has two half-passes, one that only moves vertices to parts of higher id and
+// one to lower id (so two neighbours never swap parts in one step).  In a
+// half-pass every vertex computes its best move against a snapshot of the
+// partition and part weights; the proposals are then accepted in a fixed
+// order (by target part, larger gain first, then vertex id) while the target
+// stays within the cap and the source keeps a vertex.
+struct Move {
+    int32_t v, q;
+    int64_t gain;
+};
+
 void refine_kway(const Graph& g, std::vector<int32_t>& part, int32_t nparts, int64_t cap,
-                 Rng& rng, int max_passes) {
-    std::vector<int64_t> pw(nparts, 0), conn(nparts, 0);
+                 int max_passes) {
+    std::vector<int64_t> pw(nparts, 0);
     for (int32_t v = 0; v < g.n; ++v) pw[part[v]] += g.vw[v];
-    std::vector<int32_t> touched;
-    std::vector<int32_t> order = random_order(g.n, rng);
+    const int nt = omp_get_max_threads();
+    std::vector<std::vector<Move>> local(nt);
+    std::vector<Move> props;
+    std::vector<int64_t> win(nparts), wout(nparts);
     for (int pass = 0; pass < max_passes; ++pass) {
         int64_t moves = 0;
-        for (int32_t v : order) {
-            const int32_t own = part[v];
-            const int64_t id = connectivity(g, part, v, conn, touched);
-            if (touched.empty()) continue;
-            int32_t best = -1;
-            int64_t best_ed = -1;
-            for (int32_t q : touched) {
-                if (pw[q] + g.vw[v] > cap) continue;
-                if (best < 0 || conn[q] > best_ed || (conn[q] == best_ed && pw[q] < pw[best])) {
-                    best = q;
-                    best_ed = conn[q];
+        for (int dir = 0; dir < 2; ++dir) {
+#pragma omp parallel num_threads(nt)
+            {
+                std::vector<int64_t> conn(nparts, 0);
+                std::vector<int32_t> touched;
+                std::vector<Move>& mine = local[omp_get_thread_num()];
+                mine.clear();
+#pragma omp for schedule(dynamic, 2048)
+                for (int32_t v = 0; v < g.n; ++v) {
+                    const int32_t own = part[v];
+                    const int64_t id = connectivity(g, part, v, conn, touched);
+                    if (touched.empty()) continue;
+                    int32_t best = -1;
+                    int64_t best_ed = -1;
+                    for (int32_t q : touched) {
+                        if ((dir == 0) != (q > own) || pw[q] + g.vw[v] > cap) continue;
+                        if (best < 0 || conn[q] > best_ed ||
+                            (conn[q] == best_ed && (pw[q] < pw[best] || (pw[q] == pw[best] && q < best)))) {
+                            best = q;
+                            best_ed = conn[q];
+                        }
+                    }
+                    for (int32_t q : touched) conn[q] = 0;
+                    if (best < 0) continue;
+                    const int64_t gain = best_ed - id;
+                    if (gain > 0 || (gain == 0 && pw[best] + g.vw[v] < pw[own]))
+                        mine.push_back({v, best, gain});
                 }
             }
-            for (int32_t q : touched) conn[q] = 0;
-            if (best < 0 || pw[own] - g.vw[v] <= 0) continue;
-            const int64_t gain = best_ed - id;
-            if (gain > 0 || (gain == 0 && pw[best] + g.vw[v] < pw[own])) {
-                part[v] = best;
-                pw[own] -= g.vw[v];
-                pw[best] += g.vw[v];
+            props.clear();
+            for (auto& m : local) props.insert(props.end(), m.begin(), m.end());
+            std::sort(props.begin(), props.end(), [](const Move& a, const Move& b) {
+                if (a.q != b.q) return a.q < b.q;
+                if (a.gain != b.gain) return a.gain > b.gain;
+                return a.v < b.v;
+            });
+            std::fill(win.begin(), win.end(), 0);
+            std::fill(wout.begin(), wout.end(), 0);
+            for (const Move& m : props) {
+                const int32_t own = part[m.v], w = g.vw[m.v];
+                if (pw[m.q] + win[m.q] + w > cap || pw[own] - wout[own] - w <= 0) continue;
+                // a balancing move (no gain) must still go to the lighter part
+                if (m.gain == 0 && pw[m.q] + win[m.q] + w >= pw[own] - wout[own]) continue;
+                win[m.q] += w;
+                wout[own] += w;
+                part[m.v] = m.q;
                 ++moves;
             }
+            for (int32_t q = 0; q < nparts; ++q) pw[q] += win[q] - wout[q];
         }
         if (moves * 1000 < g.n) break;
     }
@@ -454,6 +585,7 @@ Error partition_multilevel(const Graph& g0, int32_t nparts, int64_t cap, uint64_
     }
     if (nparts <= 1) return err;
     Rng rng(seed);
+    const uint64_t key = mix64(seed ^ 0x5EEDull);
     const int32_t coarsen_to = std::max<int32_t>(2000, std::min<int64_t>(40LL * nparts, n));
     const int32_t maxvw =
         (int32_t)std::max<int64_t>(1, std::min<int64_t>(cap / 3, (int64_t)(1.5 * (double)W / coarsen_to)));
@@ -463,7 +595,7 @@ Error partition_multilevel(const Graph& g0, int32_t nparts, int64_t cap, uint64_
     const Graph* cur = &g0;
     while (cur->n > coarsen_to) {
         std::vector<int32_t> cmap;
-        Graph c = coarsen(*cur, maxvw, rng, cmap);
+        Graph c = coarsen(*cur, maxvw, mix64(key + levels.size()), cmap);
         if ((double)c.n > 0.92 * (double)cur->n) break;
         cmaps.push_back(std::move(cmap));
         levels.push_back(std::move(c));
@@ -474,19 +606,22 @@ Error partition_multilevel(const Graph& g0, int32_t nparts, int64_t cap, uint64_
     {
         std::vector<int32_t> ids(cur->n);
         std::iota(ids.begin(), ids.end(), 0);
-        recursive_bisection(*cur, ids, 0, nparts, rng, cpart);
+#pragma omp parallel
+#pragma omp single
+        recursive_bisection(*cur, ids, 0, nparts, key, cpart);
     }
     balance(*cur, cpart, nparts, cap, rng);
-    refine_kway(*cur, cpart, nparts, cap, rng, 10);
+    refine_kway(*cur, cpart, nparts, cap, 10);
     // project back, refining at every level
     for (int lv = (int)levels.size() - 1; lv >= 0; --lv) {
         const Graph& fine = lv == 0 ? g0 : levels[lv - 1];
         const std::vector<int32_t>& cmap = cmaps[lv];
         std::vector<int32_t> fpart(fine.n);
+#pragma omp parallel for schedule(static)
         for (int32_t v = 0; v < fine.n; ++v) fpart[v] = cpart[cmap[v]];
         cpart.swap(fpart);
         balance(fine, cpart, nparts, cap, rng);
-        refine_kway(fine, cpart, nparts, cap, rng, lv == 0 ? 6 : 8);
+        refine_kway(fine, cpart, nparts, cap, lv == 0 ? 6 : 8);
     }
     if (levels.empty()) {
         // the coarsest graph was the input itself: already refined above

@@ -122,6 +122,21 @@ def test_determinism_same_seed():
         assert np.array_equal(a[k], b[k]), k
 
 
+@pytest.mark.parametrize("make", [lambda: matgen.knn_fem(6000, perm_seed=1, pt_seed=2, val_seed=3),
+                                  lambda: matgen.powerlaw(30000, exponent=2.3, mean_deg=10, seed=4),
+                                  lambda: matgen.stencil3d(24, perm_seed=5, val_seed=6)])
+def test_plan_independent_of_thread_count(make):
+    """The parallel partitioner and encoder give the same plan for a seed on
+    any number of host threads (matching, refinement and bisection tasks are
+    scheduled without affecting the result)."""
+    A = make()
+    ref = Plan(A, n_threads=1, seed=3).arrays()
+    for t in (2, 3, 8):
+        got = Plan(A, n_threads=t, seed=3).arrays()
+        for k in ("perm", "part_start", "halo_idx", "ell_val", "ell_col", "er_col", "ell_meta"):
+            assert np.array_equal(ref[k], got[k]), (t, k)
+
+
 def test_tiny_and_empty():
     for n in (0, 1, 2, 65):
         A = matgen.random_small(n, 0.5, 3) if n else matgen.Csr(0, 0, np.zeros(1, np.int64),
