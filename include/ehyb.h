@@ -292,6 +292,46 @@ EHYB_API ehyb_status ehyb_spmm_batched(const ehyb_batch *batch, int32_t n_rhs, c
                                       void *const *Y, uint32_t flags, void *stream);
 EHYB_API void ehyb_batch_destroy(ehyb_batch *batch);
 
+/* Preprocessing with the caller's partition instead of the built-in
+ * partitioner (Section 3.1 leaves the partitioner open; the paper uses
+ * METIS).  part: host int32 [n_rows], the partition id of each row (and of
+ * its column vertex), in [0, n_parts).  Empty ids are dropped and the rest
+ * keep their order; every partition must fit the LDS budget of `params`
+ * (at most (lds_bytes - 64) / (2 * x bytes * n_rhs) and 65535 rows), else
+ * EHYB_EINVAL.  params->slice_rows and params->partitioner are ignored; the
+ * plan reports the largest partition as its slice_rows.  A plan from the
+ * same partition and other ell_width_cap / rows_per_wave / value_dtype /
+ * halo_rows is re-encoded without re-partitioning (the partition vector of a
+ * plan follows from its perm and part_start arrays). */
+EHYB_API ehyb_status ehyb_preprocess_partitioned(const ehyb_csr_host *A, const ehyb_params *params,
+                                                const int32_t *part, int32_t n_parts, ehyb_plan **out);
+
+/* 32 sparsity features of A (square, canonical CSR as for ehyb_preprocess;
+ * values unused), the input of the learned parameter predictor, written to
+ * out[32] as float.  Row lengths r_i, mean m, population std s; quantiles
+ * are lower quantiles r_(floor(q (n-1))) of the sorted lengths:
+ *  0 log2 n            1 log2(nnz+1)        2 m          3 s
+ *  4 s/m (0 if m = 0)  5 min r              6 max r      7 log2(max r + 1)
+ *  8-13 quantiles of r at 0.10 0.25 0.50 0.75 0.90 0.99
+ * 14 skewness E[(r-m)^3]/s^3 (0 if s = 0)   15 share of empty rows
+ * 16 share of rows with r > 2m
+ * 17 mean |i-j| / n over entries            18 max |i-j| / n
+ * 19 0.90-quantile of the row bandwidth max_j |i-j| (0 for empty rows), / n
+ * 20 share of entries with |i-j| < 4096
+ * 21 mean over rows of the distinct 4096-column blocks touched
+ * 22 / 23 mean / max over 4096-row blocks of (distinct column blocks touched
+ *         / number of column blocks)
+ * 24 share of off-diagonal entries (i,j) with (j,i) stored (1 if none)
+ * 25 share of rows with a stored diagonal
+ * 26 Gini coefficient of r: sum_k (2k - n - 1) r_(k) / (n nnz), k = 1..n
+ * 27 share of entries in the ceil(n/100) longest rows
+ * 28 m / 64
+ * 29 ELL padding at width w = feature 13: sum_i (w - min(r_i, w)) / nnz
+ * 30 entries beyond width w: sum_i max(r_i - w, 0) / nnz
+ * 31 share of entries with i/512 == j/512
+ * (ratios over nnz use max(nnz, 1)).  n_threads: 0 = all. */
+EHYB_API ehyb_status ehyb_features(const ehyb_csr_host *A, int32_t n_threads, float *out);
+
 /* Save / load a plan (host arrays only) as a versioned binary file with a
  * checksum; a loaded plan must be uploaded before use.  A corrupted or
  * truncated file gives EHYB_EINVAL. */

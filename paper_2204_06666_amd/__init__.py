@@ -59,7 +59,7 @@ class Plan:
                  rows_per_wave: int = 0, value_dtype: int = EHYB_F64, lds_bytes: int = 0,
                  num_cus: int = 0, n_threads: int = 0, imbalance_pct: int = 0,
                  partitioner: int = 0, halo_rows: int = 0, n_rhs: int = 0, seed: int = 0,
-                 _handle=None):
+                 partition=None, _handle=None):
         self._lib = load()
         self._h = ctypes.c_void_p()
         self._blob = None
@@ -74,8 +74,17 @@ class Plan:
                            v.ctypes.data if v.size else None)
         prm = _abi.Params(slice_rows, ell_width_cap, rows_per_wave, value_dtype, lds_bytes,
                           num_cus, n_threads, imbalance_pct, partitioner, halo_rows, n_rhs, 0, seed)
-        check(self._lib.ehyb_preprocess(ctypes.byref(csr), ctypes.byref(prm), ctypes.byref(self._h)),
-              "ehyb_preprocess")
+        if partition is None:
+            check(self._lib.ehyb_preprocess(ctypes.byref(csr), ctypes.byref(prm), ctypes.byref(self._h)),
+                  "ehyb_preprocess")
+        else:
+            part = np.ascontiguousarray(partition, dtype=np.int32)
+            if part.shape != (A.n_rows,):
+                raise ValueError("partition must hold one id per row")
+            k = int(part.max()) + 1 if part.size else 0
+            check(self._lib.ehyb_preprocess_partitioned(ctypes.byref(csr), ctypes.byref(prm),
+                                                        part.ctypes.data if part.size else None, k,
+                                                        ctypes.byref(self._h)), "ehyb_preprocess_partitioned")
         self.n = int(A.n_rows)
         self.value_dtype = int(value_dtype)
 
@@ -127,6 +136,14 @@ class Plan:
 
     def perm(self) -> np.ndarray:
         return self.arrays()["perm"]
+
+    def partition(self) -> np.ndarray:
+        """Partition id of every original row (from perm and part_start)."""
+        a = self.arrays()
+        part = np.empty(self.n, dtype=np.int32)
+        ps = a["part_start"]
+        part[a["perm"]] = np.repeat(np.arange(ps.size - 1, dtype=np.int32), np.diff(ps))
+        return part
 
     def decode(self):
         """CSR of P A P^T (row_ptr int64, col int32, val float64)."""
@@ -250,6 +267,16 @@ class Batch:
         check(self._lib.ehyb_spmm_batched(self._h, self.n_rhs, xs, ys, EHYB_VEC_PERMUTED, _stream(stream)),
               "ehyb_spmm_batched")
         return Y
+
+
+def features(A, n_threads: int = 0) -> np.ndarray:
+    """The 32 sparsity features of A (float32), as defined by ehyb_features."""
+    rp, ci, v = _as_csr(A)
+    csr = _abi.CsrHost(A.n_rows, A.n_cols, int(rp[-1]) if rp.size else 0, rp.ctypes.data,
+                       ci.ctypes.data if ci.size else None, v.ctypes.data if v.size else None)
+    out = np.zeros(32, dtype=np.float32)
+    check(load().ehyb_features(ctypes.byref(csr), n_threads, out.ctypes.data), "ehyb_features")
+    return out
 
 
 def csr_spmv(row_ptr32, col, val, x, y, lanes_per_row: int = 0, stream=None):

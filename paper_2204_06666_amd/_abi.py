@@ -62,6 +62,9 @@ class DeviceInfo(ctypes.Structure):
 # name -> (restype, argtypes)
 SIGNATURES = {
     "ehyb_preprocess": (c_i32, [ctypes.POINTER(CsrHost), ctypes.POINTER(Params), ctypes.POINTER(c_vp)]),
+    "ehyb_preprocess_partitioned": (c_i32, [ctypes.POINTER(CsrHost), ctypes.POINTER(Params), c_vp, c_i32,
+                                            ctypes.POINTER(c_vp)]),
+    "ehyb_features": (c_i32, [ctypes.POINTER(CsrHost), c_i32, c_vp]),
     "ehyb_plan_stats_get": (c_i32, [c_vp, ctypes.POINTER(PlanStats)]),
     "ehyb_plan_arrays_get": (c_i32, [c_vp, ctypes.POINTER(PlanArrays)]),
     "ehyb_plan_decode_csr": (c_i32, [c_vp, c_vp, c_vp, c_vp]),

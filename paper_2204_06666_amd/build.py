@@ -15,7 +15,7 @@ OUT = os.path.join(HERE, "libehyb.so")
 BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SOURCES = ["ehyb_host.cpp", "partition.cpp"]
+HOST_SOURCES = ["ehyb_host.cpp", "partition.cpp", "features.cpp"]
 DEVICE_SOURCES = ["ehyb_device.hip"]
 
 CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",

@@ -578,7 +578,14 @@ const char* ehyb_last_error(void) { return g_last_error.c_str(); }
 
 const char* ehyb_version(void) { return "0.2.0"; }
 
-ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, ehyb_plan** out) {
+}  // extern "C"
+
+namespace {
+
+// Preprocessing with the built-in partitioner (given == nullptr) or with the
+// caller's partition vector.
+ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, const int32_t* given,
+                            int32_t given_nparts, ehyb_plan** out) {
     try {
         g_last_error.clear();
         if (!A || !out) return fail(EHYB_EINVAL, "null argument");
@@ -643,7 +650,31 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
         std::vector<int32_t> part;
         int32_t nparts = nparts_req;
         double t0 = now_s();
-        if (prm.partitioner == EHYB_PART_NATURAL || nparts_req <= 1) {
+        if (given) {
+            // caller's partition: ids in [0, given_nparts), every partition
+            // within the LDS budget; empty ids are dropped, order kept
+            if (given_nparts < 1 && n > 0) return fail(EHYB_EINVAL, "n_parts must be >= 1");
+            std::vector<int64_t> cnt(std::max(given_nparts, 0), 0);
+            for (int64_t i = 0; i < n; ++i) {
+                if (given[i] < 0 || given[i] >= given_nparts)
+                    return fail(EHYB_EINVAL, "partition id out of range at row " + std::to_string(i));
+                cnt[given[i]]++;
+            }
+            std::vector<int32_t> remap(cnt.size(), -1);
+            nparts = 0;
+            int64_t largest = 0;
+            for (size_t q = 0; q < cnt.size(); ++q) {
+                if (cnt[q] > max_rows)
+                    return fail(EHYB_EINVAL, "partition " + std::to_string(q) + " exceeds the LDS budget");
+                if (cnt[q] > 0) remap[q] = nparts++;
+                largest = std::max(largest, cnt[q]);
+            }
+            P->params.slice_rows = (int32_t)std::max<int64_t>(1, largest);
+            part.resize(n);
+            for (int64_t i = 0; i < n; ++i) part[i] = remap[given[i]];
+            P->t_graph = 0;
+            P->t_partition = now_s() - t0;
+        } else if (prm.partitioner == EHYB_PART_NATURAL || nparts_req <= 1) {
             part.resize(n);
             for (int64_t i = 0; i < n; ++i) part[i] = (int32_t)(i / prm.slice_rows);
             P->t_graph = 0;
@@ -679,6 +710,21 @@ ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, e
     } catch (const std::exception& ex) {
         return fail(EHYB_EINVAL, std::string("preprocessing failed: ") + ex.what());
     }
+}
+
+}  // namespace
+
+extern "C" {
+
+ehyb_status ehyb_preprocess(const ehyb_csr_host* A, const ehyb_params* params, ehyb_plan** out) {
+    return preprocess_impl(A, params, nullptr, 0, out);
+}
+
+ehyb_status ehyb_preprocess_partitioned(const ehyb_csr_host* A, const ehyb_params* params,
+                                        const int32_t* part, int32_t n_parts, ehyb_plan** out) {
+    if (!part && A && A->n_rows > 0) return fail(EHYB_EINVAL, "null partition vector");
+    static const int32_t none = 0;
+    return preprocess_impl(A, params, part ? part : &none, n_parts, out);
 }
 
 ehyb_status ehyb_plan_stats_get(const ehyb_plan* P, ehyb_plan_stats* out) {
