@@ -332,6 +332,37 @@ EHYB_API ehyb_status ehyb_preprocess_partitioned(const ehyb_csr_host *A, const e
  * (ratios over nnz use max(nnz, 1)).  n_threads: 0 = all. */
 EHYB_API ehyb_status ehyb_features(const ehyb_csr_host *A, int32_t n_threads, float *out);
 
+/* Learned parameter predictor: a fully connected network, binary32,
+ *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3,
+ * x: EHYB_MLP_IN features, hidden layers of EHYB_MLP_HIDDEN, y:
+ * EHYB_MLP_OUT outputs.  The paper picks the partition size by Eq. 1 and
+ * cites learned format selection as related work only; this network
+ * predicts (partition size, ELL width, rows per wave) from ehyb_features.
+ * params (device, EHYB_MLP_PARAMS floats): W1 [64][32] row-major, b1 [64],
+ * W2 [64][64], b2 [64], W3 [3][64], b3 [3].  X: device [batch][32],
+ * Y, T: device [batch][3], row-major.  All calls are asynchronous on
+ * `stream`; results are bitwise reproducible for a batch size. */
+#define EHYB_MLP_IN 32
+#define EHYB_MLP_HIDDEN 64
+#define EHYB_MLP_OUT 3
+#define EHYB_MLP_PARAMS 6467
+EHYB_API ehyb_status ehyb_mlp_forward(const float *params, int32_t batch, const float *X, float *Y,
+                                      void *stream);
+/* Device workspace that ehyb_mlp_grad needs for `batch` samples. */
+EHYB_API ehyb_status ehyb_mlp_workspace_bytes(int32_t batch, size_t *bytes);
+/* Mean squared error L = sum_{b,o} (y_bo - t_bo)^2 / (batch * 3) and its
+ * gradient: grad (device, EHYB_MLP_PARAMS floats, parameter layout) = dL/dparams,
+ * *loss (device float, may be NULL) = L.  The ReLU derivative at 0 is 0.
+ * workspace: device, >= ehyb_mlp_workspace_bytes(batch), caller-owned. */
+EHYB_API ehyb_status ehyb_mlp_grad(const float *params, int32_t batch, const float *X, const float *T,
+                                   float *grad, float *loss, void *workspace, size_t workspace_bytes,
+                                   void *stream);
+/* One Adam step (Kingma and Ba) in place: m, v (device, EHYB_MLP_PARAMS,
+ * zero before step 1) are the moment estimates, step >= 1 counts updates,
+ * bias corrections 1/(1 - beta^step) computed on the host in FP64. */
+EHYB_API ehyb_status ehyb_mlp_adam(float *params, const float *grad, float *m, float *v, int32_t step,
+                                   float lr, float beta1, float beta2, float eps, void *stream);
+
 /* Save / load a plan (host arrays only) as a versioned binary file with a
  * checksum; a loaded plan must be uploaded before use.  A corrupted or
  * truncated file gives EHYB_EINVAL. */

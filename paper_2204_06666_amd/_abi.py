@@ -65,6 +65,11 @@ SIGNATURES = {
     "ehyb_preprocess_partitioned": (c_i32, [ctypes.POINTER(CsrHost), ctypes.POINTER(Params), c_vp, c_i32,
                                             ctypes.POINTER(c_vp)]),
     "ehyb_features": (c_i32, [ctypes.POINTER(CsrHost), c_i32, c_vp]),
+    "ehyb_mlp_forward": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
+    "ehyb_mlp_workspace_bytes": (c_i32, [c_i32, ctypes.POINTER(ctypes.c_size_t)]),
+    "ehyb_mlp_grad": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "ehyb_mlp_adam": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, c_vp]),
     "ehyb_plan_stats_get": (c_i32, [c_vp, ctypes.POINTER(PlanStats)]),
     "ehyb_plan_arrays_get": (c_i32, [c_vp, ctypes.POINTER(PlanArrays)]),
     "ehyb_plan_decode_csr": (c_i32, [c_vp, c_vp, c_vp, c_vp]),

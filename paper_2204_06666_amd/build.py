@@ -16,7 +16,7 @@ BUILD = os.path.join(HERE, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SOURCES = ["ehyb_host.cpp", "partition.cpp", "features.cpp"]
-DEVICE_SOURCES = ["ehyb_device.hip"]
+DEVICE_SOURCES = ["ehyb_device.hip", "mlp_device.hip"]
 
 CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden", "-fopenmp", "-Wall", "-Wextra", "-Wno-unused-parameter",
             "-I", INC, "-I", CSRC]
