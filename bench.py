@@ -240,7 +240,7 @@ def main():
                                                "er_slots", "lds_bytes_used")}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": traffic, "kernel": "ehyb_spmv_f64_kernel<1>",
+                     "traffic": traffic, "kernel": "ehyb_spmv_kernel<EHYB_F64, L=1>",
                      "algorithmic_bytes_per_launch": algo, "launch_us": round(kern * 1e6, 2)},
         "cpu_baseline": cpu,
         "hbm_probe_GBps": round(hbm_meas, 1),

@@ -36,7 +36,7 @@ import numpy as np
 __all__ = [
     "Csr", "rng", "poisson2d", "stencil3d", "knn_fem", "powerlaw", "random_small",
     "uniform_vector", "integer_vector", "block_diagonal", "from_dense", "to_dense",
-    "config_matrix", "CONFIG_SEEDS", "batch_matrices",
+    "config_matrix", "CONFIG_SEEDS", "batch_matrices", "tuning_matrix",
 ]
 
 
@@ -365,3 +365,40 @@ def batch_matrices(count: int = 64, seed: int = 4000, n_lo: int = 10_000, n_hi: 
             A = knn_fem(max(50, n // 3), perm_seed=s, pt_seed=s + 200_000, val_seed=s + 100_000)
         out.append((fam, A))
     return out
+
+
+def tuning_matrix(i: int, n_lo: int = 10_000, n_hi: int = 1_000_000, seed: int = 50_000):
+    """Matrix i of the tuning set, from generator seed + i: n ~ log-uniform
+    [n_lo, n_hi]; family uniform among
+      stencil  - 2-D 5-point, 3-D 7-point or 3-D 27-point, grid sides drawn
+                 with aspect ratios ~ U[0.5, 2];
+      knn      - mutual-kNN FEM matrix, k ~ U{12..40}, 1 or 3 dof per point;
+      powerlaw - Chung-Lu, exponent ~ U[2.1, 3.0], mean degree ~ U[5, 50];
+    every matrix randomly relabelled.  Returns (description, Csr)."""
+    s = seed + i
+    g = rng(s)
+    n = float(np.exp(g.uniform(np.log(n_lo), np.log(n_hi))))
+    fam = ("stencil", "knn", "powerlaw")[int(g.integers(0, 3))]
+    if fam == "stencil":
+        kind = ("2d5", "3d7", "3d27")[int(g.integers(0, 3))]
+        if kind == "2d5":
+            r = g.uniform(0.5, 2.0)
+            nx = max(2, int(round(np.sqrt(n * r))))
+            ny = max(2, int(round(n / nx)))
+            return f"stencil-2d5 {nx}x{ny}", poisson2d(nx, ny, perm_seed=s)
+        r1, r2 = g.uniform(0.5, 2.0, 2)
+        nx = max(2, int(round((n * r1 * r1 / r2) ** (1 / 3))))
+        ny = max(2, int(round(nx * r2 / r1)))
+        nz = max(2, int(round(n / (nx * ny))))
+        pts = 7 if kind == "3d7" else 27
+        return f"stencil-3d{pts} {nx}x{ny}x{nz}", stencil3d(nx, ny, nz, points=pts, perm_seed=s,
+                                                            val_seed=s + 100_000)
+    if fam == "knn":
+        dof = (1, 3)[int(g.integers(0, 2))]
+        npts = max(100, int(round(n / dof)))
+        return f"knn dof={dof} pts={npts}", knn_fem(npts, dof=dof, perm_seed=s, pt_seed=s + 200_000,
+                                                   val_seed=s + 100_000)
+    ex = float(g.uniform(2.1, 3.0))
+    md = float(g.uniform(5.0, 50.0))
+    return f"powerlaw exp={ex:.3f} deg={md:.1f}", powerlaw(int(round(n)), exponent=ex, mean_deg=md,
+                                                           seed=s + 300_000)

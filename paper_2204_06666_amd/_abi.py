@@ -108,6 +108,12 @@ def load():
         raise RuntimeError(
             f"EHYB native library not found at {LIB_PATH}; build it with "
             "`python -c 'import __graft_entry__ as g; g.build()'` (hipcc, gfx950)")
+    # The library and torch must share one HIP runtime.  torch ships its own
+    # libamdhip64 (soname libamdhip64.so.7); once torch is imported, the
+    # library's dependency on that soname resolves to torch's copy.  Loading
+    # the library first would bring in a second runtime, which does not see
+    # torch's devices or allocations.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         f = getattr(lib, name)

@@ -1,0 +1,110 @@
+"""Exhaustive tuning of the preprocessing parameters of one matrix, and the
+sweep over the tuning set that trains the parameter predictor.
+
+For every matrix the grid is partition size x ELL width cap x rows per wave
+(6 x 4 x 4 points, FP32 values and x, one right-hand side).  The matrix is
+partitioned once per partition size; the 16 encodings of that size reuse the
+partition (ehyb_preprocess_partitioned).  Each point is timed on the device
+as the best of several rounds of back-to-back launches (HIP events).  The
+rule-based default (Eq. 1 partition size, no cap, 64 rows per wave) is timed
+beside the grid.
+
+    python -m paper_2204_06666_amd.autotune --start 0 --count 50 --out sweep.jsonl
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import EHYB_F32, Plan, features
+from .predictor import ROWS_PER_WAVE, SLICE_ROWS, WIDTH_QUANTILES, lds_max_rows, width_cap
+
+
+def time_spmv(torch, plan, x, y, launches: int = 20, rounds: int = 3) -> float:
+    """Seconds per launch: the best of `rounds` means over `launches` launches."""
+    plan.spmv(x, y)
+    torch.cuda.synchronize()
+    best = float("inf")
+    for _ in range(rounds):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(launches):
+            plan.spmv(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3 / launches)
+    return best
+
+
+def sweep_matrix(A, device="cuda:0", launches: int = 20, rounds: int = 3) -> dict:
+    """Times of every grid point and of the Eq. 1 default for matrix A."""
+    import torch
+    x = torch.from_numpy(np.random.Generator(np.random.PCG64(7)).uniform(-1, 1, A.n_rows)
+                         .astype(np.float32)).to(device)
+    y = torch.empty_like(x)
+    lens = np.diff(A.row_ptr)
+    grid = []
+    t_pre = 0.0
+    for s in SLICE_ROWS:
+        rows = s if s else lds_max_rows()
+        t0 = time.perf_counter()
+        base = Plan(A, value_dtype=EHYB_F32, slice_rows=rows)
+        part = base.partition()
+        t_pre += time.perf_counter() - t0
+        for q in WIDTH_QUANTILES:
+            for rpw in ROWS_PER_WAVE:
+                t0 = time.perf_counter()
+                if q is None and rpw == 64:
+                    p = base
+                else:
+                    p = Plan(A, value_dtype=EHYB_F32, partition=part, ell_width_cap=width_cap(lens, q),
+                             rows_per_wave=rpw)
+                t_pre += time.perf_counter() - t0
+                p.upload(device)
+                grid.append([s, q, rpw, round(time_spmv(torch, p, x, y, launches, rounds) * 1e6, 3)])
+                if p is not base:
+                    del p
+        del base
+    d = Plan(A, value_dtype=EHYB_F32).upload(device)
+    eq1 = {"slice_rows": d.stats()["slice_rows"], "time_us": round(time_spmv(torch, d, x, y, launches, rounds) * 1e6, 3)}
+    return {"grid": grid, "eq1": eq1, "preprocess_s": round(t_pre, 2)}
+
+
+def best_point(rec: dict):
+    g = min(rec["grid"], key=lambda r: r[3])
+    return g[0], g[1], g[2], g[3]
+
+
+def main(argv=None):
+    import matgen
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--start", type=int, default=0)
+    ap.add_argument("--count", type=int, default=10)
+    ap.add_argument("--n-lo", type=int, default=10_000)
+    ap.add_argument("--n-hi", type=int, default=1_000_000)
+    ap.add_argument("--out", required=True)
+    args = ap.parse_args(argv)
+    with open(args.out, "a") as f:
+        for i in range(args.start, args.start + args.count):
+            t0 = time.perf_counter()
+            desc, A = matgen.tuning_matrix(i, n_lo=args.n_lo, n_hi=args.n_hi)
+            t_gen = time.perf_counter() - t0
+            rec = {"i": i, "desc": desc, "n": int(A.n_rows), "nnz": int(A.nnz),
+                   "features": [float(v) for v in features(A)]}
+            rec.update(sweep_matrix(A))
+            f.write(json.dumps(rec) + "\n")
+            f.flush()
+            s, q, r, t = best_point(rec)
+            print(f"[autotune] {i} {desc} n={A.n_rows} nnz={A.nnz} best=({s},{q},{r}) {t:.1f}us "
+                  f"eq1 {rec['eq1']['time_us']:.1f}us gen {t_gen:.1f}s pre {rec['preprocess_s']:.1f}s "
+                  f"total {time.perf_counter() - t0:.1f}s", flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -23,7 +23,7 @@ import re
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL = "ehyb_spmv_f64_kernel"
+KERNEL = "ehyb_spmv_kernel<0, 1>"  # FP64 values (dtype 0), one lane per row
 
 
 def _one(pattern):

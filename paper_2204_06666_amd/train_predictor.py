@@ -1,0 +1,141 @@
+"""Train the parameter predictor on autotuner sweeps and judge it on held-out
+matrices.
+
+Input: JSON lines written by ``autotune`` (features, the time of every grid
+point, the time of the Eq. 1 default).  Matrices with index below
+``--n-train`` train the network; the others are held out.  The target of a
+matrix is its fastest grid point.  Features are standardised with the
+training set's mean and standard deviation (after log1p of the heavy-tailed
+ones).  Training runs on the device through the library's own forward,
+gradient and Adam kernels.
+
+For each held-out matrix the predicted point's measured time is compared with
+the exhaustive best and with the Eq. 1 default:
+
+    python -m paper_2204_06666_amd.train_predictor --sweep a.jsonl b.jsonl --n-train 256 --out model.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+
+import numpy as np
+
+from .predictor import N_IN, Mlp, decode_output, encode_target
+
+# features spanning orders of magnitude: log1p before standardising
+LOG_FEATURES = (2, 3, 5, 6, 8, 9, 10, 11, 12, 13, 28, 29)
+
+
+def load_sweeps(paths):
+    recs = {}
+    for p in paths:
+        with open(p) as f:
+            for line in f:
+                if line.strip():
+                    r = json.loads(line)
+                    recs[r["i"]] = r
+    return [recs[k] for k in sorted(recs)]
+
+
+def transform(F: np.ndarray) -> np.ndarray:
+    F = np.array(F, dtype=np.float64)
+    F[:, LOG_FEATURES] = np.log1p(np.maximum(F[:, LOG_FEATURES], 0.0))
+    return F
+
+
+def best(rec):
+    g = min(rec["grid"], key=lambda r: r[3])
+    return (g[0], g[1], g[2]), g[3]
+
+
+def time_of(rec, point):
+    for s, q, r, t in rec["grid"]:
+        if (s, q, r) == tuple(point):
+            return t
+    raise KeyError(point)
+
+
+def evaluate(recs, points):
+    """Ratios of the chosen points' times (and the Eq. 1 default's) to the best."""
+    r_pred, r_eq1 = [], []
+    for rec, pt in zip(recs, points):
+        _, tb = best(rec)
+        r_pred.append(time_of(rec, pt) / tb)
+        r_eq1.append(rec["eq1"]["time_us"] / tb)
+    r_pred, r_eq1 = np.array(r_pred), np.array(r_eq1)
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))  # noqa: E731
+    return {"n": len(recs), "geomean_pred_over_best": gm(r_pred), "geomean_eq1_over_best": gm(r_eq1),
+            "share_pred_within_1.10": float(np.mean(r_pred <= 1.10)),
+            "share_eq1_within_1.10": float(np.mean(r_eq1 <= 1.10)),
+            "worst_pred_over_best": float(r_pred.max()), "worst_eq1_over_best": float(r_eq1.max()),
+            "geomean_eq1_over_pred": gm(r_eq1 / r_pred)}
+
+
+class Predictor:
+    """Network + feature normalisation; predicts grid points from features."""
+
+    def __init__(self, params, mean, std):
+        self.params = np.asarray(params, dtype=np.float32)
+        self.mean = np.asarray(mean, dtype=np.float64)
+        self.std = np.asarray(std, dtype=np.float64)
+
+    def normalise(self, F):
+        return ((transform(np.atleast_2d(F)) - self.mean) / self.std).astype(np.float32)
+
+    def predict(self, F, device="cuda:0"):
+        import torch
+        X = torch.from_numpy(np.ascontiguousarray(self.normalise(F))).to(device)
+        Y = Mlp(self.params, device=device).forward(X).cpu().numpy()
+        return [decode_output(y) for y in Y]
+
+    def save(self, path, meta=None):
+        json.dump({"params": self.params.tolist(), "mean": self.mean.tolist(), "std": self.std.tolist(),
+                   "meta": meta or {}}, open(path, "w"))
+
+    @classmethod
+    def load(cls, path):
+        d = json.load(open(path))
+        return cls(d["params"], d["mean"], d["std"])
+
+
+def train(recs_train, epochs=400, batch=64, lr=2e-3, seed=0, device="cuda:0"):
+    import torch
+    F = transform([r["features"] for r in recs_train])
+    mean = F.mean(axis=0)
+    std = F.std(axis=0)
+    std[std == 0] = 1.0
+    X = ((F - mean) / std).astype(np.float32)
+    T = np.stack([encode_target(*best(r)[0]) for r in recs_train])
+    net = Mlp(seed=seed, device=device)
+    hist = net.fit(torch.from_numpy(X).to(device), torch.from_numpy(T).to(device), epochs, batch, lr, seed)
+    return Predictor(net.numpy_params(), mean, std), hist
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sweep", nargs="+", required=True)
+    ap.add_argument("--n-train", type=int, required=True)
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--batch", type=int, default=64)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    recs = load_sweeps(args.sweep)
+    tr = [r for r in recs if r["i"] < args.n_train]
+    te = [r for r in recs if r["i"] >= args.n_train]
+    pred, hist = train(tr, args.epochs, args.batch, args.lr, args.seed)
+    res = {"train_loss_first": hist[0], "train_loss_last": hist[-1],
+           "train": evaluate(tr, pred.predict([r["features"] for r in tr])),
+           "held_out": evaluate(te, pred.predict([r["features"] for r in te])) if te else None}
+    print(json.dumps(res), flush=True)
+    if args.out:
+        pred.save(args.out, {"n_train": len(tr), "n_held_out": len(te), "epochs": args.epochs,
+                             "batch": args.batch, "lr": args.lr, "seed": args.seed, "result": res})
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
