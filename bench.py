@@ -85,11 +85,18 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "knn-fem", "batched"],
+    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "knn-fem", "batched", "predictor"],
                     help="stencil27: the headline FP64 product (default); knn-fem: the "
                          "unstructured-FEM matrix in FP64, FP32 and BF16 values; batched: 64 "
-                         "uneven FP32 matrices x 8 right-hand sides in one launch")
+                         "uneven FP32 matrices x 8 right-hand sides in one launch; predictor: the "
+                         "learned preprocessing parameters on held-out matrices")
     ap.add_argument("--count", type=int, default=64, help="batched only: number of matrices")
+    ap.add_argument("--lds-bytes", type=int, default=0,
+                    help="batched only: LDS budget per partition (0 = 160 KiB; 80 KiB lets two "
+                         "workgroups share a CU)")
+    ap.add_argument("--halo-rows", type=int, default=0, help="batched only: halo_rows of the plans")
+    ap.add_argument("--rows-per-wave", type=int, default=64, help="batched only: rows_per_wave (64, 16 or 4)")
+    ap.add_argument("--live", type=int, default=16, help="predictor only: held-out matrices re-timed live")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="knn-fem only: fraction of the 1e6 points")
     args = ap.parse_args()
@@ -101,6 +108,8 @@ def main():
         return run_precision(args)
     if args.workload == "batched":
         return run_batched(args)
+    if args.workload == "predictor":
+        return run_predictor(args)
 
     import numpy as np
     import torch
@@ -359,7 +368,8 @@ def run_batched(args):
     t0 = time.perf_counter()
     plans = []
     for i, (_, A) in enumerate(mats):
-        plans.append(Plan(A, value_dtype=EHYB_F32, n_rhs=nrhs).upload(dev))
+        plans.append(Plan(A, value_dtype=EHYB_F32, n_rhs=nrhs, lds_bytes=args.lds_bytes,
+                          halo_rows=args.halo_rows, rows_per_wave=args.rows_per_wave).upload(dev))
         if i % 16 == 15:
             log(f"  {i + 1} plans built")
     t_pre = time.perf_counter() - t0
@@ -460,6 +470,8 @@ def run_batched(args):
         "data": "synthetic",
         "config": {"workload": f"{args.count} matrices, n log-uniform in [1e4, 5e5], 2-D Poisson / "
                                f"27-point stencil / kNN-FEM 3 dof (seeds 4000+i), 8 RHS ~ U[-1,1], FP32",
+                   "plan": {"lds_bytes": args.lds_bytes or 160 * 1024, "halo_rows": args.halo_rows,
+                            "rows_per_wave": args.rows_per_wave},
                    "sum_n": sum_n, "sum_nnz": sum_nnz, "work_items": sum(p.stats()["nparts"] for p in plans)},
         "roofline": {"bound": "hbm", "achieved": round(algo / kern_g / 1e9, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(algo / kern_g / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
@@ -472,6 +484,79 @@ def run_batched(args):
         "speedup_vs_separate_graph": round(wall_sg / wall_g, 2),
         "max_row_scaled_error_vs_quantized": worst,
         "preprocess_s": round(t_pre, 1),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def run_predictor(args):
+    """Learned preprocessing parameters (NEXT-3).  The network is trained here,
+    on the device with the library's own kernels, on the committed sweep of
+    the training matrices; the held-out matrices are judged on their recorded
+    sweep times, and a sample of them is re-generated and re-timed live
+    (predicted point, Eq. 1 default, recorded best)."""
+    import numpy as np
+    import torch
+
+    import matgen
+    from paper_2204_06666_amd import EHYB_F32, Plan, features
+    from paper_2204_06666_amd.autotune import time_spmv
+    from paper_2204_06666_amd.predictor import lds_max_rows, width_cap
+    from paper_2204_06666_amd.train_predictor import Predictor, best, evaluate, load_sweeps, train
+
+    data = os.path.join(ROOT, "paper_2204_06666_amd", "data")
+    model = json.load(open(os.path.join(data, "predictor_fp32.json")))
+    meta = model["meta"]
+    recs = load_sweeps([os.path.join(data, "tuning_sweep.jsonl")])
+    tr = [r for r in recs if r["i"] < meta["n_train"]]
+    te = [r for r in recs if r["i"] >= meta["n_train"]]
+    log(f"{len(tr)} training and {len(te)} held-out matrices; training on the device")
+    t0 = time.perf_counter()
+    pred, hist = train(tr, meta["epochs"], meta["batch"], meta["lr"], meta["seed"], meta.get("near", 0.0))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    same = bool(np.array_equal(pred.params, np.asarray(model["params"], dtype=np.float32)))
+    points = pred.predict([r["features"] for r in te])
+    held = evaluate(te, points)
+    log(f"held-out (recorded times): {held}")
+    live = []
+    k = min(args.live, len(te))
+    for rec, pt in list(zip(te, points))[:k]:
+        desc, A = matgen.tuning_matrix(rec["i"], n_hi=250_000)
+        f = features(A)
+        if not np.allclose(f, rec["features"], rtol=1e-5, atol=1e-6):
+            raise SystemExit(f"features of matrix {rec['i']} differ from the recorded sweep")
+        lens = np.diff(A.row_ptr)
+        x = torch.from_numpy(matgen.uniform_vector(A.n_rows, 7).astype(np.float32)).to("cuda:0")
+        y = torch.empty_like(x)
+
+        def plan_for(point):
+            s, q, r = point
+            base = Plan(A, value_dtype=EHYB_F32, slice_rows=s or lds_max_rows())
+            return Plan(A, value_dtype=EHYB_F32, partition=base.partition(), ell_width_cap=width_cap(lens, q),
+                        rows_per_wave=r).upload("cuda:0")
+
+        tp = time_spmv(torch, plan_for(pt), x, y, 50, 5)
+        tb = time_spmv(torch, plan_for(best(rec)[0]), x, y, 50, 5)
+        te1 = time_spmv(torch, Plan(A, value_dtype=EHYB_F32).upload("cuda:0"), x, y, 50, 5)
+        live.append({"i": rec["i"], "desc": desc, "pred_us": round(tp * 1e6, 2), "best_us": round(tb * 1e6, 2),
+                     "eq1_us": round(te1 * 1e6, 2)})
+        log(f"  live {live[-1]}")
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))  # noqa: E731
+    live_sum = {"n": len(live),
+                "geomean_pred_over_best": gm([l["pred_us"] / l["best_us"] for l in live]) if live else None,
+                "geomean_eq1_over_pred": gm([l["eq1_us"] / l["pred_us"] for l in live]) if live else None}
+    out = {
+        "metric": "learned EHYB parameters: held-out geomean SpMV time / exhaustive-grid best",
+        "value": round(held["geomean_pred_over_best"], 4), "unit": "x", "n_gpus": 1,
+        "steps": len(te), "warmup": 0, "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"tuning set: {len(tr)} training + {len(te)} held-out matrices, n log-uniform "
+                               f"in [1e4, 2.5e5], stencil / kNN-FEM / power-law families (seeds 50000+i); grid "
+                               f"6 partition sizes x 4 ELL width caps x 4 rows-per-wave, FP32",
+                   "network": "32 -> 64 -> 64 -> 3, ReLU, binary32, Adam"},
+        "held_out": held, "live": live_sum, "live_matrices": live,
+        "train_s": round(t_train, 2), "train_loss": [hist[0], hist[-1]],
+        "retrained_params_equal_committed": same,
     }
     print(json.dumps(out), flush=True)
 

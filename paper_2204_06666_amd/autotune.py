@@ -2,7 +2,8 @@
 sweep over the tuning set that trains the parameter predictor.
 
 For every matrix the grid is partition size x ELL width cap x rows per wave
-(6 x 4 x 4 points, FP32 values and x, one right-hand side).  The matrix is
+(6 x 4 x 4 points, FP32 values and x, one right-hand side; the values are in
+``predictor``).  The matrix is
 partitioned once per partition size; the 16 encodings of that size reuse the
 partition (ehyb_preprocess_partitioned).  Each point is timed on the device
 as the best of several rounds of back-to-back launches (HIP events).  The
@@ -41,13 +42,14 @@ def time_spmv(torch, plan, x, y, launches: int = 20, rounds: int = 3) -> float:
 
 
 def sweep_matrix(A, device="cuda:0", launches: int = 20, rounds: int = 3) -> dict:
-    """Times of every grid point and of the Eq. 1 default for matrix A."""
+    """Times (us) of every grid point, as times_us[slice][width][rows per
+    wave] in the order of the grid tuples, and of the Eq. 1 default."""
     import torch
     x = torch.from_numpy(np.random.Generator(np.random.PCG64(7)).uniform(-1, 1, A.n_rows)
                          .astype(np.float32)).to(device)
     y = torch.empty_like(x)
     lens = np.diff(A.row_ptr)
-    grid = []
+    times = []
     t_pre = 0.0
     for s in SLICE_ROWS:
         rows = s if s else lds_max_rows()
@@ -55,7 +57,9 @@ def sweep_matrix(A, device="cuda:0", launches: int = 20, rounds: int = 3) -> dic
         base = Plan(A, value_dtype=EHYB_F32, slice_rows=rows)
         part = base.partition()
         t_pre += time.perf_counter() - t0
+        per_s = []
         for q in WIDTH_QUANTILES:
+            per_q = []
             for rpw in ROWS_PER_WAVE:
                 t0 = time.perf_counter()
                 if q is None and rpw == 64:
@@ -65,18 +69,30 @@ def sweep_matrix(A, device="cuda:0", launches: int = 20, rounds: int = 3) -> dic
                              rows_per_wave=rpw)
                 t_pre += time.perf_counter() - t0
                 p.upload(device)
-                grid.append([s, q, rpw, round(time_spmv(torch, p, x, y, launches, rounds) * 1e6, 3)])
+                per_q.append(round(time_spmv(torch, p, x, y, launches, rounds) * 1e6, 2))
                 if p is not base:
                     del p
+            per_s.append(per_q)
+        times.append(per_s)
         del base
     d = Plan(A, value_dtype=EHYB_F32).upload(device)
-    eq1 = {"slice_rows": d.stats()["slice_rows"], "time_us": round(time_spmv(torch, d, x, y, launches, rounds) * 1e6, 3)}
-    return {"grid": grid, "eq1": eq1, "preprocess_s": round(t_pre, 2)}
+    eq1 = {"slice_rows": d.stats()["slice_rows"], "time_us": round(time_spmv(torch, d, x, y, launches, rounds) * 1e6, 2)}
+    return {"slice_rows": list(SLICE_ROWS), "width_q": list(WIDTH_QUANTILES), "rows_per_wave": list(ROWS_PER_WAVE),
+            "times_us": times, "eq1": eq1, "preprocess_s": round(t_pre, 2)}
+
+
+def grid_points(rec: dict):
+    """[(slice_rows, width_q, rows_per_wave, time_us)] of a sweep record."""
+    out = []
+    for i, s in enumerate(rec["slice_rows"]):
+        for j, q in enumerate(rec["width_q"]):
+            for k, r in enumerate(rec["rows_per_wave"]):
+                out.append((s, q, r, rec["times_us"][i][j][k]))
+    return out
 
 
 def best_point(rec: dict):
-    g = min(rec["grid"], key=lambda r: r[3])
-    return g[0], g[1], g[2], g[3]
+    return min(grid_points(rec), key=lambda g: g[3])
 
 
 def main(argv=None):
@@ -86,7 +102,7 @@ def main(argv=None):
     ap.add_argument("--start", type=int, default=0)
     ap.add_argument("--count", type=int, default=10)
     ap.add_argument("--n-lo", type=int, default=10_000)
-    ap.add_argument("--n-hi", type=int, default=1_000_000)
+    ap.add_argument("--n-hi", type=int, default=250_000)
     ap.add_argument("--out", required=True)
     args = ap.parse_args(argv)
     with open(args.out, "a") as f:
@@ -95,7 +111,7 @@ def main(argv=None):
             desc, A = matgen.tuning_matrix(i, n_lo=args.n_lo, n_hi=args.n_hi)
             t_gen = time.perf_counter() - t0
             rec = {"i": i, "desc": desc, "n": int(A.n_rows), "nnz": int(A.nnz),
-                   "features": [float(v) for v in features(A)]}
+                   "features": [float(f"{v:.7g}") for v in features(A)]}
             rec.update(sweep_matrix(A))
             f.write(json.dumps(rec) + "\n")
             f.flush()

@@ -873,14 +873,19 @@ ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* co
         a.Y[i] = Y[i];
     }
     if (a.n_items == 0) return EHYB_OK;
+    // Two workgroups per CU when two partitions' LDS fit, so that one
+    // workgroup's staging (latency-bound gathers) overlaps the other's
+    // streaming; they then have 8 wavefronts each (16 per CU, which the
+    // kernels' register use allows), else one workgroup of 16.
     const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024 - kStaticLds) / std::max<int64_t>(1, B->lds_bytes)));
+    const int threads = per_cu >= 2 ? 512 : 1024;
     const int nblocks = std::min(a.n_items, 256 * per_cu);
     bool ok = false;
     hipStream_t s = (hipStream_t)stream;
     switch (B->value_dtype) {
-        case EHYB_F64: ok = launch_batched_dt<EHYB_F64>(B->L, n_rhs, a, nblocks, 1024, (size_t)B->lds_bytes, s); break;
-        case EHYB_F32: ok = launch_batched_dt<EHYB_F32>(B->L, n_rhs, a, nblocks, 1024, (size_t)B->lds_bytes, s); break;
-        case EHYB_BF16: ok = launch_batched_dt<EHYB_BF16>(B->L, n_rhs, a, nblocks, 1024, (size_t)B->lds_bytes, s); break;
+        case EHYB_F64: ok = launch_batched_dt<EHYB_F64>(B->L, n_rhs, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
+        case EHYB_F32: ok = launch_batched_dt<EHYB_F32>(B->L, n_rhs, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
+        case EHYB_BF16: ok = launch_batched_dt<EHYB_BF16>(B->L, n_rhs, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
         default: break;
     }
     if (!ok) return fail(EHYB_EUNSUPPORTED, "no batched kernel for this value type, rows_per_wave and n_rhs");

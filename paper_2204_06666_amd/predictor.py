@@ -20,8 +20,10 @@ N_IN, N_HID, N_OUT, N_PARAMS = 32, 64, 3, 6467
 SHAPES = [("W1", (N_HID, N_IN)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2", (N_HID,)),
           ("W3", (N_OUT, N_HID)), ("b3", (N_OUT,))]
 
-# the tuning grid (FP32 values, one right-hand side)
-SLICE_ROWS = (1024, 2048, 4096, 8192, 16384, 0)   # 0: the LDS limit ((160 KiB - 64) / 8 rows)
+# the tuning grid (FP32 values, one right-hand side).  Partition sizes reach
+# down to 256 rows so that matrices of 10^4 - 10^5 rows can still spread over
+# the 256 CUs; 0 is the LDS limit ((160 KiB - 64) / 8 rows).
+SLICE_ROWS = (256, 512, 1024, 2048, 4096, 0)
 WIDTH_QUANTILES = (None, 0.99, 0.90, 0.75)        # ELL width cap: none or a row-length quantile
 ROWS_PER_WAVE = (8, 16, 32, 64)
 

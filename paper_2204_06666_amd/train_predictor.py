@@ -22,7 +22,8 @@ import sys
 
 import numpy as np
 
-from .predictor import N_IN, Mlp, decode_output, encode_target
+from .autotune import best_point, grid_points
+from .predictor import Mlp, decode_output, encode_target
 
 # features spanning orders of magnitude: log1p before standardising
 LOG_FEATURES = (2, 3, 5, 6, 8, 9, 10, 11, 12, 13, 28, 29)
@@ -46,15 +47,26 @@ def transform(F: np.ndarray) -> np.ndarray:
 
 
 def best(rec):
-    g = min(rec["grid"], key=lambda r: r[3])
-    return (g[0], g[1], g[2]), g[3]
+    s, q, r, t = best_point(rec)
+    return (s, q, r), t
 
 
 def time_of(rec, point):
-    for s, q, r, t in rec["grid"]:
+    for s, q, r, t in grid_points(rec):
         if (s, q, r) == tuple(point):
             return t
     raise KeyError(point)
+
+
+def target(rec, near: float = 0.0) -> np.ndarray:
+    """Network target of a matrix: the encoding of its fastest grid point, or
+    (near > 0) the mean encoding of every point within (1 + near) x the
+    fastest time, which is less sensitive to timing noise among near ties."""
+    pts = grid_points(rec)
+    tb = min(p[3] for p in pts)
+    if near <= 0:
+        return encode_target(*best(rec)[0])
+    return np.mean([encode_target(s, q, r) for s, q, r, t in pts if t <= (1 + near) * tb], axis=0)
 
 
 def evaluate(recs, points):
@@ -100,14 +112,14 @@ class Predictor:
         return cls(d["params"], d["mean"], d["std"])
 
 
-def train(recs_train, epochs=400, batch=64, lr=2e-3, seed=0, device="cuda:0"):
+def train(recs_train, epochs=400, batch=64, lr=2e-3, seed=0, near=0.0, device="cuda:0"):
     import torch
     F = transform([r["features"] for r in recs_train])
     mean = F.mean(axis=0)
     std = F.std(axis=0)
     std[std == 0] = 1.0
     X = ((F - mean) / std).astype(np.float32)
-    T = np.stack([encode_target(*best(r)[0]) for r in recs_train])
+    T = np.stack([target(r, near) for r in recs_train]).astype(np.float32)
     net = Mlp(seed=seed, device=device)
     hist = net.fit(torch.from_numpy(X).to(device), torch.from_numpy(T).to(device), epochs, batch, lr, seed)
     return Predictor(net.numpy_params(), mean, std), hist
@@ -121,19 +133,22 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--near", type=float, default=0.0,
+                    help="target = mean encoding of the points within (1 + near) x the best time")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     recs = load_sweeps(args.sweep)
     tr = [r for r in recs if r["i"] < args.n_train]
     te = [r for r in recs if r["i"] >= args.n_train]
-    pred, hist = train(tr, args.epochs, args.batch, args.lr, args.seed)
+    pred, hist = train(tr, args.epochs, args.batch, args.lr, args.seed, args.near)
     res = {"train_loss_first": hist[0], "train_loss_last": hist[-1],
            "train": evaluate(tr, pred.predict([r["features"] for r in tr])),
            "held_out": evaluate(te, pred.predict([r["features"] for r in te])) if te else None}
     print(json.dumps(res), flush=True)
     if args.out:
         pred.save(args.out, {"n_train": len(tr), "n_held_out": len(te), "epochs": args.epochs,
-                             "batch": args.batch, "lr": args.lr, "seed": args.seed, "result": res})
+                             "batch": args.batch, "lr": args.lr, "seed": args.seed, "near": args.near,
+                             "result": res})
     return 0
 
 

@@ -1,0 +1,55 @@
+"""The exhaustive sweep and the predictor end to end on small matrices."""
+import numpy as np
+import pytest
+
+import matgen
+from paper_2204_06666_amd import EHYB_F32, Plan, features
+from paper_2204_06666_amd.autotune import best_point, grid_points, sweep_matrix
+from paper_2204_06666_amd.predictor import ROWS_PER_WAVE, SLICE_ROWS, WIDTH_QUANTILES, width_cap
+from paper_2204_06666_amd.train_predictor import evaluate, train
+
+pytestmark = pytest.mark.gpu
+
+
+def test_sweep_record_and_plans():
+    A = matgen.powerlaw(3000, exponent=2.3, mean_deg=8, seed=5)
+    rec = sweep_matrix(A, launches=3, rounds=1)
+    t = np.array(rec["times_us"])
+    assert t.shape == (len(SLICE_ROWS), len(WIDTH_QUANTILES), len(ROWS_PER_WAVE)) and np.all(t > 0)
+    assert len(grid_points(rec)) == t.size and best_point(rec)[3] == t.min()
+    assert rec["eq1"]["time_us"] > 0
+    # a grid point's plan computes the product (re-encoded from a given partition)
+    import torch
+    s, q, r, _ = best_point(rec)
+    base = Plan(A, value_dtype=EHYB_F32, slice_rows=s or 20472)
+    P = Plan(A, value_dtype=EHYB_F32, partition=base.partition(),
+             ell_width_cap=width_cap(np.diff(A.row_ptr), q), rows_per_wave=r).upload("cuda:0")
+    x = matgen.uniform_vector(A.n_rows, 3).astype(np.float32)
+    y = P.spmv(torch.from_numpy(x).to("cuda:0"), permuted=False).cpu().numpy().astype(np.float64)
+    Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, A.val.astype(np.float32).astype(np.float64))
+    ref = matgen.to_dense(Aq) @ x.astype(np.float64)
+    assert np.allclose(y, ref, rtol=1e-4, atol=1e-4 * np.abs(ref).max())
+
+
+def test_predictor_learns_a_rule():
+    """Synthetic sweep records whose best point is a fixed function of two
+    features: the trained network recovers it on held-out records."""
+    g = matgen.rng(1)
+    recs = []
+    base_f = features(matgen.poisson2d(30))
+    for i in range(160):
+        f = base_f.astype(np.float64).copy()
+        f[0] = g.uniform(10, 20)          # log2 n
+        f[16] = g.uniform(0, 1)           # share of heavy rows
+        si = int(np.clip((f[0] - 10) / 10 * 6, 0, 5))
+        ri = 0 if f[16] > 0.5 else 3
+        times = np.full((6, 4, 4), 10.0)
+        times[si, 0, ri] = 5.0
+        recs.append({"i": i, "features": f.tolist(), "slice_rows": list(SLICE_ROWS),
+                     "width_q": list(WIDTH_QUANTILES), "rows_per_wave": list(ROWS_PER_WAVE),
+                     "times_us": times.tolist(), "eq1": {"time_us": 10.0}})
+    pred, hist = train(recs[:128], epochs=150, batch=32, lr=3e-3)
+    res = evaluate(recs[128:], pred.predict([r["features"] for r in recs[128:]]))
+    print(f"[predictor] synthetic held-out: {res}", flush=True)
+    assert hist[-1] < 0.2 * hist[0]
+    assert res["share_pred_within_1.10"] >= 0.8

@@ -36,11 +36,11 @@ def _check(A, X, Y, dt, what):
     assert ok.all(), f"{what}: max err {err[~ok].max():.3e}"
 
 
-def _run(dt, n_rhs, rpw=64, halo=0):
+def _run(dt, n_rhs, rpw=64, halo=0, lds=160 * 1024):
     mats = _mats()
     # about three partitions per matrix, within the LDS budget of n_rhs-wide rows
-    cap = (160 * 1024 - 64) // (2 * (8 if dt == EHYB_F64 else 4) * n_rhs)
-    plans = [Plan(A, value_dtype=dt, n_rhs=n_rhs, rows_per_wave=rpw, halo_rows=halo,
+    cap = (lds - 64) // (2 * (8 if dt == EHYB_F64 else 4) * n_rhs)
+    plans = [Plan(A, value_dtype=dt, n_rhs=n_rhs, rows_per_wave=rpw, halo_rows=halo, lds_bytes=lds,
                   slice_rows=max(64, min(A.n_rows // 3, cap))).upload("cuda:0") for A in mats]
     g = matgen.rng(11)
     X = [g.uniform(-1, 1, (A.n_rows, n_rhs)) for A in mats]
@@ -68,6 +68,15 @@ def test_batched_parity(dt, n_rhs, rpw, halo):
         Y = _unperm(p, y.cpu().numpy().astype(np.float64))
         _check(A, x, Y, dt, f"dt={dt} n_rhs={n_rhs} rpw={rpw} halo={halo} n={A.n_rows}")
     print(f"[batched] dt={dt} n_rhs={n_rhs} rpw={rpw} halo={halo} ok", flush=True)
+
+
+@pytest.mark.parametrize("dt,n_rhs", [(EHYB_F32, 8), (EHYB_F64, 4)])
+def test_batched_two_workgroups_per_cu(dt, n_rhs):
+    """Plans within half the LDS: the launch runs two 8-wavefront workgroups per CU."""
+    mats, plans, X, Xd, Yd, B = _run(dt, n_rhs, lds=80 * 1024)
+    for A, p, x, y in zip(mats, plans, X, Yd):
+        assert p.stats()["lds_bytes_used"] * n_rhs <= 80 * 1024
+        _check(A, x, _unperm(p, y.cpu().numpy().astype(np.float64)), dt, f"80 KiB dt={dt} n_rhs={n_rhs}")
 
 
 def test_repeated_launches_identical():
