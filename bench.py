@@ -91,9 +91,9 @@ def main():
                          "uneven FP32 matrices x 8 right-hand sides in one launch; predictor: the "
                          "learned preprocessing parameters on held-out matrices")
     ap.add_argument("--count", type=int, default=64, help="batched only: number of matrices")
-    ap.add_argument("--lds-bytes", type=int, default=0,
-                    help="batched only: LDS budget per partition (0 = 160 KiB; 80 KiB lets two "
-                         "workgroups share a CU)")
+    ap.add_argument("--lds-bytes", type=int, default=80 * 1024,
+                    help="batched only: LDS budget per partition (80 KiB lets two workgroups share a "
+                         "CU; 0 = 160 KiB)")
     ap.add_argument("--halo-rows", type=int, default=0, help="batched only: halo_rows of the plans")
     ap.add_argument("--rows-per-wave", type=int, default=64, help="batched only: rows_per_wave (64, 16 or 4)")
     ap.add_argument("--live", type=int, default=16, help="predictor only: held-out matrices re-timed live")

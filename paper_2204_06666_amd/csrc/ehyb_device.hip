@@ -873,12 +873,13 @@ ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* co
         a.Y[i] = Y[i];
     }
     if (a.n_items == 0) return EHYB_OK;
-    // Two workgroups per CU when two partitions' LDS fit, so that one
-    // workgroup's staging (latency-bound gathers) overlaps the other's
-    // streaming; they then have 8 wavefronts each (16 per CU, which the
-    // kernels' register use allows), else one workgroup of 16.
-    const int per_cu = (int)std::max<int64_t>(1, std::min<int64_t>(2, (160 * 1024 - kStaticLds) / std::max<int64_t>(1, B->lds_bytes)));
-    const int threads = per_cu >= 2 ? 512 : 1024;
+    // Up to four workgroups per CU when their partitions' LDS fits, so that
+    // one workgroup's staging (latency-bound gathers) overlaps the others'
+    // streaming; the CU's 16 wavefronts are split among them (16, 8, 5 or
+    // 4 per workgroup, within what the kernels' register use allows).
+    const int per_cu = (int)std::max<int64_t>(
+        1, std::min<int64_t>(4, (160 * 1024) / std::max<int64_t>(1, B->lds_bytes + kStaticLds)));
+    const int threads = 64 * (16 / per_cu);
     const int nblocks = std::min(a.n_items, 256 * per_cu);
     bool ok = false;
     hipStream_t s = (hipStream_t)stream;

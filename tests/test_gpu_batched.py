@@ -71,12 +71,14 @@ def test_batched_parity(dt, n_rhs, rpw, halo):
 
 
 @pytest.mark.parametrize("dt,n_rhs", [(EHYB_F32, 8), (EHYB_F64, 4)])
-def test_batched_two_workgroups_per_cu(dt, n_rhs):
-    """Plans within half the LDS: the launch runs two 8-wavefront workgroups per CU."""
-    mats, plans, X, Xd, Yd, B = _run(dt, n_rhs, lds=80 * 1024)
+@pytest.mark.parametrize("lds", [80 * 1024, 53 * 1024, 40 * 1024])
+def test_batched_several_workgroups_per_cu(dt, n_rhs, lds):
+    """Plans within a half, a third or a quarter of the LDS: the launch runs
+    two, three or four workgroups of 8, 5 or 4 wavefronts per CU."""
+    mats, plans, X, Xd, Yd, B = _run(dt, n_rhs, lds=lds)
     for A, p, x, y in zip(mats, plans, X, Yd):
-        assert p.stats()["lds_bytes_used"] * n_rhs <= 80 * 1024
-        _check(A, x, _unperm(p, y.cpu().numpy().astype(np.float64)), dt, f"80 KiB dt={dt} n_rhs={n_rhs}")
+        assert p.stats()["lds_bytes_used"] * n_rhs <= lds
+        _check(A, x, _unperm(p, y.cpu().numpy().astype(np.float64)), dt, f"{lds} B dt={dt} n_rhs={n_rhs}")
 
 
 def test_repeated_launches_identical():

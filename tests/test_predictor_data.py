@@ -1,0 +1,49 @@
+"""The committed tuning sweep and trained predictor: format, consistency with
+the generator and the grid, and the held-out result stored with the model
+(host only)."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import matgen
+from paper_2204_06666_amd import features
+from paper_2204_06666_amd.predictor import N_PARAMS, ROWS_PER_WAVE, SLICE_ROWS, WIDTH_QUANTILES
+from paper_2204_06666_amd.train_predictor import load_sweeps
+
+DATA = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2204_06666_amd", "data")
+SWEEP = os.path.join(DATA, "tuning_sweep.jsonl")
+MODEL = os.path.join(DATA, "predictor_fp32.json")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(SWEEP), reason="no committed sweep")
+
+
+def test_sweep_records():
+    recs = load_sweeps([SWEEP])
+    assert [r["i"] for r in recs] == list(range(len(recs)))
+    for r in recs:
+        assert r["slice_rows"] == list(SLICE_ROWS) and r["rows_per_wave"] == list(ROWS_PER_WAVE)
+        assert r["width_q"] == list(WIDTH_QUANTILES)
+        t = np.array(r["times_us"])
+        assert t.shape == (6, 4, 4) and np.all(t > 0) and r["eq1"]["time_us"] > 0
+        assert len(r["features"]) == 32
+
+
+@pytest.mark.parametrize("i", [0, 3, 6, 9])
+def test_recorded_features_match_the_generator(i):
+    recs = {r["i"]: r for r in load_sweeps([SWEEP])}
+    desc, A = matgen.tuning_matrix(i, n_hi=250_000)
+    assert desc == recs[i]["desc"] and A.n_rows == recs[i]["n"] and A.nnz == recs[i]["nnz"]
+    np.testing.assert_allclose(features(A), recs[i]["features"], rtol=1e-6, atol=1e-9)
+
+
+def test_model_file():
+    if not os.path.exists(MODEL):
+        pytest.skip("no committed model")
+    d = json.load(open(MODEL))
+    assert len(d["params"]) == N_PARAMS and len(d["mean"]) == 32 and len(d["std"]) == 32
+    m = d["meta"]
+    n = len(load_sweeps([SWEEP]))
+    assert 0 < m["n_train"] < n and m["n_held_out"] == n - m["n_train"]
+    assert m["result"]["held_out"]["n"] == n - m["n_train"]
