@@ -31,10 +31,10 @@ def kernel_source_hash():
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def load_traffic(kernel_hash):
+def load_traffic(kernel_hash, name="ehyb_spmv_f64_stencil27_traffic.json"):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, only if
     they were taken on the current kernel source."""
-    p = os.path.join(ROOT, "profiles", "ehyb_spmv_f64_stencil27_traffic.json")
+    p = os.path.join(ROOT, "profiles", name)
     try:
         d = json.load(open(p))
     except (OSError, ValueError):
@@ -474,7 +474,9 @@ def run_batched(args):
                             "rows_per_wave": args.rows_per_wave},
                    "sum_n": sum_n, "sum_nnz": sum_nnz, "work_items": sum(p.stats()["nparts"] for p in plans)},
         "roofline": {"bound": "hbm", "achieved": round(algo / kern_g / 1e9, 1), "peak": PEAK_HBM_GBPS,
-                     "unit": "GB/s", "frac": round(algo / kern_g / 1e9 / PEAK_HBM_GBPS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(algo / kern_g / 1e9 / PEAK_HBM_GBPS, 4),
+                     "traffic": load_traffic(kernel_source_hash(), "ehyb_spmm_batched_f32x8_64mat_traffic.json"),
+                     "kernel": "ehyb_spmm_batched_kernel<EHYB_F32, L=1, NRHS=8>",
                      "algorithmic_bytes": algo, "launch_us": round(kern_g * 1e6, 2)},
         "cpu_baseline": cpu,
         "batched_eager_us": round(wall_e * 1e6, 2),

@@ -1,7 +1,8 @@
 """Fixed kernel sequence for hardware-counter runs (rocprofv3 --pmc).
 
-Runs the headline EHYB FP64 product `--reps` times and the copy probe on a
-buffer of known size `--reps` times, nothing else on the GPU, so that the
+Runs the headline EHYB FP64 product (or, with ``--workload batched``, the
+batched product of 64 FP32 matrices x 8 right-hand sides) `--reps` times and
+the copy probe on a buffer of known size `--reps` times, nothing else on the GPU, so that the
 per-dispatch FETCH_SIZE / WRITE_SIZE of each kernel can be read off and the
 EHYB counters scaled by what the same counters report for the copy of a known
 number of bytes.
@@ -20,6 +21,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "batched"])
     args = ap.parse_args()
     import torch
 
@@ -28,22 +30,36 @@ def main():
     from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS
 
     dev = torch.device("cuda:0")
-    A = matgen.config_matrix(HEADLINE["config"])
-    x = matgen.uniform_vector(A.n_rows, HEADLINE["x_seed"])
-    plan = Plan(A, **HEADLINE_PARAMS).upload(dev)
-    st = plan.stats()
-    xp = torch.from_numpy(x[plan.perm()]).to(dev)
-    yp = torch.empty_like(xp)
+    if args.workload == "stencil27":
+        A = matgen.config_matrix(HEADLINE["config"])
+        x = matgen.uniform_vector(A.n_rows, HEADLINE["x_seed"])
+        plan = Plan(A, **HEADLINE_PARAMS).upload(dev)
+        algo = plan.stats()["algorithmic_bytes"]
+        xp = torch.from_numpy(x[plan.perm()]).to(dev)
+        yp = torch.empty_like(xp)
+        run = lambda: plan.spmv(xp, yp)  # noqa: E731
+    else:
+        from paper_2204_06666_amd import EHYB_F32, Batch
+        from paper_2204_06666_amd.workloads import BATCHED_PARAMS
+        nrhs = BATCHED_PARAMS["n_rhs"]
+        mats = [A for _, A in matgen.batch_matrices(64)]
+        plans = [Plan(A, value_dtype=EHYB_F32, **BATCHED_PARAMS).upload(dev) for A in mats]
+        batch = Batch(plans, nrhs, dev)
+        g = matgen.rng(4999)
+        Xd = [torch.from_numpy(g.uniform(-1, 1, (A.n_rows, nrhs)).astype("float32")).to(dev) for A in mats]
+        Yd = [torch.empty_like(v) for v in Xd]
+        algo = sum(p.stats()["algorithmic_bytes"] + 2 * (nrhs - 1) * p.n * 4 for p in plans)
+        run = lambda: batch.spmm(Xd, Yd)  # noqa: E731
     src = torch.ones((args.copy_mib << 20) // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
     for _ in range(args.reps):
-        plan.spmv(xp, yp)
+        run()
     torch.cuda.synchronize()
     for _ in range(args.reps):
         probe_copy(src, dst)
     torch.cuda.synchronize()
-    print(f"ehyb algorithmic_bytes={st['algorithmic_bytes']} copy_bytes_read={src.numel() * 4} "
+    print(f"ehyb algorithmic_bytes={algo} copy_bytes_read={src.numel() * 4} "
           f"copy_bytes_written={dst.numel() * 4} reps={args.reps}", flush=True)
 
 

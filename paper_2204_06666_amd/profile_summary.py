@@ -23,7 +23,7 @@ import re
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL = "ehyb_spmv_kernel<0, 1>"  # FP64 values (dtype 0), one lane per row
+KERNEL = "ehyb_spmv_kernel<0, 1>"  # FP64 values (dtype 0), one lane per row (--kernel overrides)
 
 
 def _one(pattern):
@@ -38,23 +38,23 @@ def kernel_source_hash():
     return hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
 
 
-def trace_summary(trace_dir, warmup, steps, top=10):
+def trace_summary(trace_dir, warmup, steps, kernel=KERNEL, top=10):
     stats = list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_stats.csv")))))
     rows = list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_trace.csv")))))
-    ehyb = sorted((r for r in rows if KERNEL in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
+    ehyb = sorted((r for r in rows if kernel in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
     dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in ehyb]
     window = dur[warmup:warmup + steps]
     return stats[:top], (statistics.mean(window) if window else None), len(ehyb)
 
 
-def pmc_values(pmc_dir, counter):
+def pmc_values(pmc_dir, counter, kernel=KERNEL):
     rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "**", "*counter_collection.csv")))))
     out = {}
     for r in rows:
         if r["Counter_Name"] != counter:
             continue
         name = r["Kernel_Name"]
-        key = KERNEL if KERNEL in name else ("copy" if "probe_copy_kernel" in name else None)
+        key = "ehyb" if kernel in name else ("copy" if "probe_copy_kernel" in name else None)
         if key:
             out.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
     return {k: statistics.mean(v) for k, v in out.items()}
@@ -72,21 +72,25 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic", required=True)
     ap.add_argument("--commands", default="", help="the commands that produced the inputs")
+    ap.add_argument("--kernel", default=KERNEL, help="substring of the kernel name to summarise")
+    ap.add_argument("--title", default="EHYB FP64 SpMV, 27-point stencil 100^3 (1e6 rows, 26,463,592 nnz)")
+    ap.add_argument("--workload-name", default="stencil27-100^3")
     args = ap.parse_args()
+    kernel = args.kernel
 
-    stats, window_ns, n_disp = trace_summary(args.trace, args.warmup, args.steps)
+    stats, window_ns, n_disp = trace_summary(args.trace, args.warmup, args.steps, kernel)
     log = open(args.fetch_log).read()
     m = re.search(r"ehyb algorithmic_bytes=(\d+) copy_bytes_read=(\d+) copy_bytes_written=(\d+)", log)
     algo, copy_r, copy_w = (int(g) for g in m.groups())
-    fetch = pmc_values(args.fetch, "FETCH_SIZE")
-    write = pmc_values(args.write, "WRITE_SIZE")
+    fetch = pmc_values(args.fetch, "FETCH_SIZE", kernel)
+    write = pmc_values(args.write, "WRITE_SIZE", kernel)
     f_scale = copy_r / fetch["copy"]
     w_scale = copy_w / write["copy"]
-    traffic = fetch[KERNEL] * f_scale + write[KERNEL] * w_scale
+    traffic = fetch["ehyb"] * f_scale + write["ehyb"] * w_scale
     kh = kernel_source_hash()
     bench = json.load(open(args.bench_json)) if args.bench_json else None
 
-    lines = ["# rocprofv3 summary: EHYB FP64 SpMV, 27-point stencil 100^3 (1e6 rows, 26,463,592 nnz)", ""]
+    lines = [f"# rocprofv3 summary: {args.title}", ""]
     if args.commands:
         lines += ["Commands (run from the repository root on one MI355X):", "", "```", args.commands.strip(),
                   "```", ""]
@@ -98,29 +102,28 @@ def main():
         name = (name[5:] if name.startswith("void ") else name).split("(")[0][:60] or "(unnamed)"
         lines.append(f"| `{name}` | {s['Calls']} | {float(s['AverageNs']) / 1e3:.2f} | "
                      f"{float(s['MinNs']) / 1e3:.2f} | {float(s['MaxNs']) / 1e3:.2f} |")
-    lines += ["", f"EHYB dispatches traced: {n_disp}. The benchmark's timed window is dispatches "
-                  f"{args.warmup}..{args.warmup + args.steps - 1} of the headline plan (after "
-                  f"{args.warmup} warm-up launches); their mean duration is "
-                  f"**{window_ns / 1e3:.2f} us**."]
+    lines += ["", f"Dispatches of `{kernel}` traced: {n_disp}. The benchmark's timed window is "
+                  f"dispatches {args.warmup}..{args.warmup + args.steps - 1} (after {args.warmup} "
+                  f"warm-up launches); their mean duration is **{window_ns / 1e3:.2f} us**."]
     if bench:
         lines.append(f"bench.py measured {bench['roofline']['launch_us']} us per launch with HIP "
                      f"events in the same run ({bench['value']} GFLOP/s).")
-        lines.append("The kernel's overall average above also includes the cold-cache launches and "
-                     "the no-halo plan, which run the same kernel symbol.")
+        lines.append("The kernel's overall average above also includes every other launch of the same "
+                     "kernel symbol in that run.")
     lines += ["", "## HBM traffic per launch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
               f"Copy probe of {copy_r} bytes: FETCH_SIZE reads {fetch['copy']:.0f} bytes "
               f"(scale {f_scale:.4f}), WRITE_SIZE {write['copy']:.0f} bytes (scale {w_scale:.4f}).", "",
               f"| quantity | bytes |", "|---|---|",
-              f"| FETCH_SIZE x scale | {fetch[KERNEL] * f_scale:.0f} |",
-              f"| WRITE_SIZE x scale | {write[KERNEL] * w_scale:.0f} |",
+              f"| FETCH_SIZE x scale | {fetch['ehyb'] * f_scale:.0f} |",
+              f"| WRITE_SIZE x scale | {write['ehyb'] * w_scale:.0f} |",
               f"| traffic per launch | {traffic:.0f} |",
               f"| algorithmic bytes per launch | {algo} |",
               f"| traffic / algorithmic | {traffic / algo:.3f} |", ""]
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     open(args.out, "w").write("\n".join(lines) + "\n")
-    json.dump({"kernel": KERNEL, "workload": "stencil27-100^3", "kernel_source_sha256_16": kh,
-               "bytes_per_launch": round(traffic), "fetch_bytes": round(fetch[KERNEL] * f_scale),
-               "write_bytes": round(write[KERNEL] * w_scale), "fetch_scale": f_scale,
+    json.dump({"kernel": kernel, "workload": args.workload_name, "kernel_source_sha256_16": kh,
+               "bytes_per_launch": round(traffic), "fetch_bytes": round(fetch["ehyb"] * f_scale),
+               "write_bytes": round(write["ehyb"] * w_scale), "fetch_scale": f_scale,
                "write_scale": w_scale, "algorithmic_bytes": algo,
                "timed_window_avg_us": round(window_ns / 1e3, 3)},
               open(args.traffic, "w"), indent=1)
