@@ -249,7 +249,7 @@ def main():
                                                "er_slots", "lds_bytes_used")}},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
-                     "traffic": traffic, "kernel": "ehyb_spmv_kernel<EHYB_F64, L=1>",
+                     "traffic": traffic, "kernel": "ehyb_spmv_kernel<EHYB_F64, L=1, plain loads>",
                      "algorithmic_bytes_per_launch": algo, "launch_us": round(kern * 1e6, 2)},
         "cpu_baseline": cpu,
         "hbm_probe_GBps": round(hbm_meas, 1),
@@ -476,7 +476,7 @@ def run_batched(args):
         "roofline": {"bound": "hbm", "achieved": round(algo / kern_g / 1e9, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(algo / kern_g / 1e9 / PEAK_HBM_GBPS, 4),
                      "traffic": load_traffic(kernel_source_hash(), "ehyb_spmm_batched_f32x8_64mat_traffic.json"),
-                     "kernel": "ehyb_spmm_batched_kernel<EHYB_F32, L=1, NRHS=8>",
+                     "kernel": "ehyb_spmm_batched_kernel<EHYB_F32, L=1, NRHS=8, streaming loads>",
                      "algorithmic_bytes": algo, "launch_us": round(kern_g * 1e6, 2)},
         "cpu_baseline": cpu,
         "batched_eager_us": round(wall_e * 1e6, 2),

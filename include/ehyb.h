@@ -66,6 +66,16 @@ typedef enum {
     EHYB_PART_NATURAL = 1     /* consecutive blocks of the given row order */
 } ehyb_partitioner;
 
+/* How the kernels load the value and column arrays, which every product reads
+ * once: AUTO = non-temporal (streaming) loads when the product's bytes exceed
+ * 384 MiB (1.5x the 256 MB Infinity Cache), plain loads otherwise, so that
+ * repeated products of a smaller plan can hit that cache. */
+typedef enum {
+    EHYB_LOAD_AUTO = 0,
+    EHYB_LOAD_CACHED = 1,
+    EHYB_LOAD_STREAM = 2
+} ehyb_load_mode;
+
 /* Input matrix in canonical CSR (host memory, borrowed for the call).
  * n_rows == n_cols (the graph reading of Section 3.1 needs a square matrix:
  * otherwise EHYB_EUNSUPPORTED).  row_ptr[0] == 0, row_ptr non-decreasing,
@@ -255,6 +265,8 @@ EHYB_API ehyb_status ehyb_spmv(const ehyb_plan *plan, const void *x, void *y, ui
  * ehyb_spmv calls on this plan; does not change results (each row is summed by
  * one fixed lane group in one fixed order whatever the shape). */
 EHYB_API ehyb_status ehyb_plan_set_launch(ehyb_plan *plan, int32_t waves_per_wg);
+/* Load mode (ehyb_load_mode) of ehyb_spmv for this plan; results are unchanged. */
+EHYB_API ehyb_status ehyb_plan_set_load_mode(ehyb_plan *plan, int32_t mode);
 
 /* x_perm[i] = x[perm[i]] and y[perm[i]] = y_perm[i] on the device (the
  * reordering applied to vectors; FP64 for FP64 plans). */
@@ -290,6 +302,9 @@ EHYB_API ehyb_status ehyb_batch_upload(ehyb_batch *batch, void *dev_blob, size_t
  * must not overlap in time (they share its queue counters). */
 EHYB_API ehyb_status ehyb_spmm_batched(const ehyb_batch *batch, int32_t n_rhs, const void *const *X,
                                       void *const *Y, uint32_t flags, void *stream);
+/* Load mode (ehyb_load_mode) of ehyb_spmm_batched, judged on the batch's
+ * total bytes; results are unchanged. */
+EHYB_API ehyb_status ehyb_batch_set_load_mode(ehyb_batch *batch, int32_t mode);
 EHYB_API void ehyb_batch_destroy(ehyb_batch *batch);
 
 /* Preprocessing with the caller's partition instead of the built-in

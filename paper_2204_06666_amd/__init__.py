@@ -17,11 +17,13 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import (EHYB_BF16, EHYB_F32, EHYB_F64, EHYB_VEC_PERMUTED, EhybError,  # noqa: F401
+from ._abi import (EHYB_BF16, EHYB_F32, EHYB_F64, EHYB_LOAD_AUTO, EHYB_LOAD_CACHED,  # noqa: F401
+                   EHYB_LOAD_STREAM, EHYB_VEC_PERMUTED, EhybError,
                    check, load)
 
 __all__ = ["Plan", "Batch", "csr_spmv", "probe_read", "probe_copy", "device_info", "version",
-           "EhybError", "EHYB_F64", "EHYB_F32", "EHYB_BF16", "EHYB_VEC_PERMUTED", "load"]
+           "EhybError", "EHYB_F64", "EHYB_F32", "EHYB_BF16", "EHYB_VEC_PERMUTED", "EHYB_LOAD_AUTO",
+           "EHYB_LOAD_CACHED", "EHYB_LOAD_STREAM", "load"]
 
 _NP_VAL = {EHYB_F64: np.float64, EHYB_F32: np.float32, EHYB_BF16: np.uint16}
 
@@ -175,6 +177,11 @@ class Plan:
         check(self._lib.ehyb_plan_set_launch(self._h, waves_per_wg), "set_launch")
         return self
 
+    def set_load_mode(self, mode: int = 0):
+        """EHYB_LOAD_AUTO / _CACHED / _STREAM loads of the value and column arrays."""
+        check(self._lib.ehyb_plan_set_load_mode(self._h, mode), "set_load_mode")
+        return self
+
     # ---------------------------------------------------------- device side
     def upload(self, device="cuda:0", stream=None):
         """Allocate the device blob with torch and copy the plan into it."""
@@ -251,6 +258,11 @@ class Batch:
         if h is not None and h.value:
             self._lib.ehyb_batch_destroy(h)
             self._h = ctypes.c_void_p()
+
+    def set_load_mode(self, mode: int = 0):
+        """EHYB_LOAD_AUTO / _CACHED / _STREAM loads of the value and column arrays."""
+        check(self._lib.ehyb_batch_set_load_mode(self._h, mode), "set_load_mode")
+        return self
 
     def spmm(self, X, Y, stream=None):
         """Y[i] = A_i X[i] for every matrix (lists of CUDA tensors [n_i, n_rhs])."""

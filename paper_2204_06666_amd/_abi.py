@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "EHYB_OK", -1: "EHYB_EINVAL", -2: "EHYB_ENOMEM", -3: "EHYB_EU
                 -4: "EHYB_EDEVICE", -5: "EHYB_ESTATE"}
 EHYB_F64, EHYB_F32, EHYB_BF16 = 0, 1, 2
 EHYB_VEC_PERMUTED = 1
+EHYB_LOAD_AUTO, EHYB_LOAD_CACHED, EHYB_LOAD_STREAM = 0, 1, 2
 
 
 class CsrHost(ctypes.Structure):
@@ -77,6 +78,8 @@ SIGNATURES = {
     "ehyb_plan_upload": (c_i32, [c_vp, c_vp, c_size, c_vp]),
     "ehyb_spmv": (c_i32, [c_vp, c_vp, c_vp, c_u32, c_vp]),
     "ehyb_plan_set_launch": (c_i32, [c_vp, c_i32]),
+    "ehyb_plan_set_load_mode": (c_i32, [c_vp, c_i32]),
+    "ehyb_batch_set_load_mode": (c_i32, [c_vp, c_i32]),
     "ehyb_permute_x": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "ehyb_unpermute_y": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "ehyb_plan_save": (c_i32, [c_vp, ctypes.c_char_p]),

@@ -109,6 +109,7 @@ struct ehyb_plan {
     double t_graph = 0, t_partition = 0, t_reorder = 0, t_encode = 0;
     int32_t n_rhs = 1;             // right-hand sides the LDS budget is sized for
     int32_t launch_waves = 0;      // 0 = automatic launch shape
+    int32_t load_mode = 0;         // ehyb_load_mode of ehyb_spmv
     // device binding (non-owning)
     void* dev_blob = nullptr;
     size_t dev_bytes = 0;
@@ -124,6 +125,7 @@ struct ehyb_batch {
     void* dev_blob = nullptr;
     int64_t lds_bytes = 0;           // dynamic LDS of one workgroup
     int64_t algorithmic_bytes = 0;   // sum over matrices, n_rhs-wide x and y
+    int32_t load_mode = 0;           // ehyb_load_mode of ehyb_spmm_batched
 };
 
 namespace ehyb {

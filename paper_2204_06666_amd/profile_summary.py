@@ -23,7 +23,8 @@ import re
 import statistics
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-KERNEL = "ehyb_spmv_kernel<0, 1>"  # FP64 values (dtype 0), one lane per row (--kernel overrides)
+# FP64 values (dtype 0), one lane per row, plain loads (--kernel overrides)
+KERNEL = "ehyb_spmv_kernel<0, 1, false>"
 
 
 def _one(pattern):

@@ -81,6 +81,16 @@ def test_batched_several_workgroups_per_cu(dt, n_rhs, lds):
         _check(A, x, _unperm(p, y.cpu().numpy().astype(np.float64)), dt, f"{lds} B dt={dt} n_rhs={n_rhs}")
 
 
+def test_batched_load_modes_identical():
+    from paper_2204_06666_amd import EHYB_LOAD_CACHED, EHYB_LOAD_STREAM
+    mats, plans, X, Xd, Yd, B = _run(EHYB_F32, 8)
+    B.set_load_mode(EHYB_LOAD_CACHED).spmm(Xd, Yd)
+    a = [y.clone() for y in Yd]
+    B.set_load_mode(EHYB_LOAD_STREAM).spmm(Xd, Yd)
+    for u, v in zip(a, Yd):
+        assert torch.equal(u.view(torch.int32), v.view(torch.int32))
+
+
 def test_repeated_launches_identical():
     mats, plans, X, Xd, Yd, B = _run(EHYB_F32, 8)
     first = [y.clone() for y in Yd]

@@ -7,7 +7,8 @@ import pytest
 
 import matgen
 import oracle
-from paper_2204_06666_amd import EhybError, Plan, _abi, csr_spmv, probe_copy, probe_read
+from paper_2204_06666_amd import (EHYB_LOAD_CACHED, EHYB_LOAD_STREAM, EhybError, Plan, _abi, csr_spmv, probe_copy,
+                                  probe_read)
 from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS, PAPER_SPLIT_PARAMS
 
 pytestmark = pytest.mark.gpu
@@ -110,6 +111,27 @@ def test_bitwise_determinism(torch, halo):
         y = P.spmv(x)
         assert torch.equal(y.view(torch.int64), y0.view(torch.int64))
     print("[parity] determinism ok", flush=True)
+
+
+@pytest.mark.parametrize("value_dtype", [0, 1, 2])
+@pytest.mark.parametrize("rpw,halo", [(64, 0), (16, -1)])
+def test_load_modes_give_same_bits(torch, value_dtype, rpw, halo):
+    """Streaming and plain loads of the value and column arrays: identical
+    results, and within the tolerance of the oracle (FP64 plans)."""
+    A = matgen.knn_fem(2000, perm_seed=1, pt_seed=2, val_seed=3)
+    P = Plan(A, slice_rows=1500, value_dtype=value_dtype, rows_per_wave=rpw, halo_rows=halo).upload("cuda:0")
+    x = matgen.uniform_vector(A.n_rows, 5)
+    xd = _dev(torch, x[P.perm()].astype(np.float64 if value_dtype == 0 else np.float32))
+    yc = P.set_load_mode(EHYB_LOAD_CACHED).spmv(xd).clone()
+    ys = P.set_load_mode(EHYB_LOAD_STREAM).spmv(xd).clone()
+    P.set_load_mode(0)
+    assert torch.equal(yc, ys)
+    if value_dtype == 0:
+        y = np.empty(A.n_rows)
+        y[P.perm()] = ys.cpu().numpy()
+        _check(A, x, y, f"stream loads rpw={rpw} halo={halo}")
+    with pytest.raises(EhybError):
+        P.set_load_mode(3)
 
 
 def test_plan_file_gives_same_bits(torch, tmp_path):
