@@ -94,8 +94,13 @@ typedef struct {
                                0 = Eq. 1-2: smallest K with n*tau/(K*P) < lds_bytes,
                                VecSize = ceil(n/(K*P)), floored at min(n, 512).
                                At most lds_bytes/tau and 65536 rows. */
-    int32_t ell_width_cap;  /* max ELL entries per row; 0 = unlimited (the
-                               paper's split by partition only) */
+    int32_t ell_width_cap;  /* max ELL entries per row: > 0 as given; -1 =
+                               unlimited (the paper's split by partition
+                               only); 0 = automatic, 128 load steps per lane
+                               group (128 * lanes per row * kc entries), which
+                               only hub rows reach: their excess entries go
+                               to the residual part, where they run on wide
+                               slices */
     int32_t rows_per_wave;  /* rows per 64-lane wavefront row-slice, a power of
                                two in [1, 64]; 64/rows_per_wave lanes share a
                                row. 0 = 64 (one lane per row) */
@@ -153,7 +158,9 @@ typedef struct {
     int32_t max_halo;         /* largest halo of one partition */
     int32_t lds_bytes_used;   /* LDS one workgroup of ehyb_spmv uses */
     int32_t n_rhs;            /* right-hand sides the plan is sized for */
-    int32_t reserved2;
+    int32_t n_er_wide;        /* wide residual slices (one long row, 64 lanes) */
+    int32_t ell_width_cap;    /* ELL width cap in effect, 0 = none */
+    int32_t reserved3;
     double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */
 } ehyb_plan_stats;
 
@@ -182,18 +189,22 @@ typedef struct {
  * residual part.
  *
  * Residual part: the rows of partition p with residual entries, sorted by
- * non-increasing residual count (ties by local row), are cut into row-slices
- * of C rows, slices [er_slice_start[p], er_slice_start[p+1]); er_row[e*C + r]
- * is the local row of row r of residual slice e (0xFFFF past the last row).
- * er_meta[2e..2e+1] = slot offset, step count.  Columns are permuted global
- * indices.
+ * non-increasing residual count (ties by local row), slices
+ * [er_slice_start[p], er_slice_start[p+1]).  When C > 1, each row with more
+ * than 32*L residual entries (they come first) has a "wide" slice of its
+ * own, processed by all 64 lanes; the other rows are cut into row-slices of
+ * C rows.  er_row[e*C + r] is the local row of row r of residual slice e
+ * (0xFFFF past the last row; a wide slice names its row at r = 0).
+ * er_meta[2e..2e+1] = slot offset, step count (bit 31 set for a wide slice).
+ * Columns are permuted global indices.
  *
  * Slots: entry k (ascending permuted column) of row r of a slice with slot
  * offset `off` lives at
  *   t = k / (L*KC), u = (k / KC) % L, c = k % KC, lane = r*L + u,
  *   slot = off + (t*64 + lane)*KC + c,
- * with KC = kc in the ELL part and KC = 1 in the residual part.  Each step of
- * a slice holds 64*KC slots.  Padding slots hold +0.0 and column 0. */
+ * with KC = kc in the ELL part and KC = 1 in the residual part; in a wide
+ * residual slice, L = 64 and r = 0 (entry k at off + k).  Each step of a
+ * slice holds 64*KC slots.  Padding slots hold +0.0 and column 0. */
 typedef struct {
     int64_t n;
     int32_t nparts, nslices, ner_slices, lanes_per_row, kc, value_dtype;

@@ -25,7 +25,9 @@ step).  ELL part: partition p's rows, in order, cut into row-slices; row r of
 an ELL slice with index j is local row j*C + r.  Residual part: the rows
 of partition p that have residual entries, by non-increasing residual count
 (ties by local row), cut into row-slices; row r of residual slice e is local
-row er_row[e, r] (0xFFFF: none).  In either part
+row er_row[e, r] (0xFFFF: none).  When C > 1, every residual row with more
+than 32*L residual entries comes first, in a "wide" slice of its own (bit 31
+of its step count, row at r = 0) laid out as if L were 64.  In either part
 
     entry k (ascending column) of row r of a slice with slot offset `off` lives at
         t = k // (L*KC), u = (k // KC) % L, c = k % KC, lane = r*L + u,
@@ -39,7 +41,7 @@ halo_idx[halo_start[p] + c - size].
 ``view`` is a mapping with the keys: n, nparts, L, kc, perm, part_start,
 halo_start, halo_idx, slice_start, er_slice_start, ell_free, ell_meta (uint32 [nslices, 4]: offset,
 steps | slice index << 16, residual-row mask low/high; slices without residual
-rows first), er_meta (uint32 [ner_slices, 2]: offset, steps),
+rows first), er_meta (uint32 [ner_slices, 2]: offset, steps | wide << 31),
 er_row (uint16 [ner_slices, C]), ell_val, ell_col (uint16), er_val, er_col
 (int32), row_ell_len, row_er_len.
 """
@@ -57,9 +59,13 @@ def _req(cond, msg):
         raise PlanError(msg)
 
 
+WIDE = 1 << 31        # step-count flag of a wide residual slice
+WIDE_STEPS = 32      # a residual row longer than WIDE_STEPS * L entries is wide
+
+
 def _slice_rows(view, which: str):
-    """Per slice: (slot offset, steps, partition, rows[C]) with rows the
-    permuted row of each slice row or -1."""
+    """Per slice: (slot offset, steps, partition, rows[C], wide) with rows the
+    permuted row of each slice row or -1, and wide the wide-slice flag."""
     L = int(view["L"])
     C = 64 // L
     part_start = np.asarray(view["part_start"], dtype=np.int64)
@@ -81,11 +87,13 @@ def _slice_rows(view, which: str):
         local = j[:, None] * C + np.arange(C)[None, :]
         size = (part_start[part + 1] - part_start[part])[:, None]
         rows = np.where(local < size, part_start[part][:, None] + local, -1)
+        wide = np.zeros(ns, dtype=bool)
     else:
-        steps = meta[:, 1]
+        steps = meta[:, 1] & (WIDE - 1)
+        wide = (meta[:, 1] & WIDE) != 0
         er_row = np.asarray(view["er_row"], dtype=np.int64).reshape(ns, C)
         rows = np.where(er_row != 0xFFFF, part_start[part][:, None] + er_row, -1)
-    return meta[:, 0], steps, part, rows
+    return meta[:, 0], steps, part, rows, wide
 
 
 def _slots(view, which: str):
@@ -96,7 +104,7 @@ def _slots(view, which: str):
     the row, whether it holds a real entry, and the slice's partition."""
     L = int(view["L"])
     kc = int(view["kc"]) if which == "ell" else 1
-    off, steps, part_of_slice, rows = _slice_rows(view, which)
+    off, steps, part_of_slice, rows, wide = _slice_rows(view, which)
     rowlen = np.asarray(view["row_ell_len"] if which == "ell" else view["row_er_len"],
                         dtype=np.int64)
     nslices = off.shape[0]
@@ -107,9 +115,10 @@ def _slots(view, which: str):
     t = o // (64 * kc)
     lane = (o // kc) % 64
     c = o % kc
-    r = lane // L
-    u = lane % L
-    k = (t * L + u) * kc + c
+    Ls = np.where(wide[s_of], 64, L)     # lanes per row of each slot's slice
+    r = lane // Ls
+    u = lane % Ls
+    k = (t * Ls + u) * kc + c
     row = rows[s_of, r] if total else np.zeros(0, dtype=np.int64)
     exists = row >= 0
     valid = exists.copy()
@@ -240,21 +249,34 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
     # non-increasing residual count, ties by local row, padding at the end
     er_row = np.asarray(view["er_row"], dtype=np.int64).reshape(-1, C)
     er_start = np.asarray(view["er_slice_start"], dtype=np.int64)
+    er_wide = (np.asarray(view["er_meta"], dtype=np.int64).reshape(-1, 2)[:, 1] & WIDE) != 0
     for p in range(nparts):
-        rows_p = er_row[er_start[p]:er_start[p + 1]].reshape(-1)
-        real = rows_p[rows_p != 0xFFFF]
-        _req(np.array_equal(rows_p[:real.size], real), "residual padding rows before real rows")
+        a, b = er_start[p], er_start[p + 1]
+        w = er_wide[a:b]
+        nw = int(w.sum())
+        _req(not w[nw:].any(), "wide residual slices are not first")
+        _req(nw == 0 or C > 1, "wide residual slice with one row per slice")
+        _req((er_row[a:a + nw, 0] != 0xFFFF).all() and (er_row[a:a + nw, 1:] == 0xFFFF).all(),
+             "a wide residual slice must hold exactly one row, at r = 0")
+        rows_n = er_row[a + nw:b].reshape(-1)
+        real_n = rows_n[rows_n != 0xFFFF]
+        _req(np.array_equal(rows_n[:real_n.size], real_n), "residual padding rows before real rows")
+        real = np.concatenate([er_row[a:a + nw, 0], real_n])
         want = np.nonzero(row_er_len[part_start[p]:part_start[p + 1]] > 0)[0]
         _req(real.size == want.size and np.array_equal(np.sort(real), want),
              "residual rows are not exactly the rows with residual entries")
-        _req(rows_p.size == -(-want.size // C) * C, "residual slices per partition")
+        lens_p = row_er_len[part_start[p] + real]
+        long_rows = int((lens_p > WIDE_STEPS * L).sum()) if C > 1 else 0
+        _req(nw == long_rows and (lens_p[:nw] > WIDE_STEPS * L).all(),
+             "wide residual slices are not exactly the rows longer than 32 * L entries")
+        _req(rows_n.size == -(-(want.size - nw) // C) * C, "residual slices per partition")
         cnt = row_er_len[part_start[p] + real]
         _req((np.diff(cnt) <= 0).all(), "residual rows not in non-increasing residual count")
         tie = np.diff(cnt) == 0
         _req((np.diff(real)[tie] > 0).all(), "residual rows: unstable tie order")
 
     for which, arr, width in (("ell", ell_val, 64 * kc), ("er", er_val, 64)):
-        off, steps, part_of_slice, rows = _slice_rows(view, which)
+        off, steps, part_of_slice, rows, wide = _slice_rows(view, which)
         end = off + steps * width
         _req((end <= arr.size).all(), "slot range past the end of its array")
         o = np.argsort(off, kind="stable")
@@ -262,7 +284,7 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
         _req((off[o][nz][1:] >= end[o][nz][:-1]).all(), "overlapping slot ranges")
         # minimal widths: each slice's step count is what its longest row needs
         lens = row_ell_len if which == "ell" else row_er_len
-        per = L * kc if which == "ell" else L
+        per = L * kc if which == "ell" else np.where(wide, 64, L)
         rl = np.where(rows >= 0, lens[np.maximum(rows, 0)], 0)
         need = rl.max(axis=1) if rl.size else np.zeros(0, dtype=np.int64)
         _req(np.array_equal(steps, -(-need // per)), f"{which} slice width is not its longest row")
@@ -346,6 +368,7 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
         "nnz": int(B.nnz), "nnz_ell": int(in_ell.sum()), "nnz_er": nnz_er,
         "nnz_halo": int((in_ell & ~same).sum()), "n_halo": int(halo_idx.size),
         "ell_slots": int((np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)[:, 1] & 0xFFFF).sum() * 64 * kc),
-        "er_slots": int(np.asarray(view["er_meta"], dtype=np.int64).reshape(-1, 2)[:, 1].sum() * 64),
+        "er_slots": int((np.asarray(view["er_meta"], dtype=np.int64).reshape(-1, 2)[:, 1] & (WIDE - 1)).sum() * 64),
+        "n_er_wide": int(er_wide.sum()),
         "er_fraction": nnz_er / max(1, B.nnz), "nparts": nparts,
     }

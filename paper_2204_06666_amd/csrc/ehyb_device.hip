@@ -231,8 +231,10 @@ struct Queues {
 //     columns and values (up to kErChunk steps at once), gathers x from
 //     device memory for all of them, and leaves each row's sums in LDS
 //     accumulators (each residual row belongs to one lane group: plain
-//     store), then counts the slice.  The next slice's metadata is fetched
-//     while the current one is processed;
+//     store), then counts the slice.  A residual row too long for its lane
+//     group has a wide slice of its own, which all 64 lanes take and reduce
+//     (so a hub row of a power-law matrix is not left to L lanes).  The next
+//     slice's metadata is fetched while the current one is processed;
 //  3. ELL queue (slices without residual rows first): a wavefront takes a
 //     row-slice, issues all its loads (up to kEll steps of 16 bytes of values
 //     and KC columns per lane) before using any, multiply-adds against the
@@ -354,10 +356,12 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
             const int itn = wave_fetch_add(&Q.q_er, lane);
             const uint2 mn = itn < ner ? a.er_meta[e0 + itn] : make_uint2(0, 0);
             const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
-            const uint32_t steps = __builtin_amdgcn_readfirstlane(m.y);
+            const uint32_t my = __builtin_amdgcn_readfirstlane(m.y);
+            const uint32_t steps = my & ~kErWide;
+            const bool wide = (my & kErWide) != 0;  // one long row on all 64 lanes
             const V* ev = er_val + off + lane;
             const int32_t* ec = a.er_col + off + lane;
-            const uint16_t lr = a.er_row[(size_t)(e0 + it) * C + r];
+            const uint16_t lr = a.er_row[(size_t)(e0 + it) * C + (wide ? 0 : r)];
             Acc acc[NRHS];
 #pragma unroll
             for (int k = 0; k < NRHS; ++k) acc[k] = 0;
@@ -382,9 +386,14 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
                         for (int k = 0; k < NRHS; ++k) acc[k] = fma(vv, (Acc)lane_of<X, NRHS>(xg[j], k), acc[k]);
                     }
             }
+            if (wide) {
 #pragma unroll
-            for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<L>(acc[k]);
-            if ((lane & (L - 1)) == 0 && lr != 0xFFFF) {
+                for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<kWave>(acc[k]);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<L>(acc[k]);
+            }
+            if ((wide ? lane == 0 : (lane & (L - 1)) == 0) && lr != 0xFFFF) {
 #pragma unroll
                 for (int k = 0; k < NRHS; ++k) yer[(size_t)lr * NRHS + k] = acc[k];
             }

@@ -405,14 +405,27 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
             return P->row_er_len[ps + a] > P->row_er_len[ps + b];
         });
     }
-    for (int32_t p = 0; p < nparts; ++p)
-        P->er_slice_start[p + 1] = P->er_slice_start[p] + (int32_t)((er_rows[p].size() + C - 1) / C);
+    // rows longer than kWideSteps steps on their L lanes (the first ones,
+    // counts are non-increasing) get a wide slice each; the rest C per slice
+    std::vector<int32_t> er_nwide(nparts, 0);
+    for (int32_t p = 0; p < nparts; ++p) {
+        const int32_t ps = P->part_start[p];
+        if (C > 1)
+            while (er_nwide[p] < (int32_t)er_rows[p].size() &&
+                   P->row_er_len[ps + er_rows[p][er_nwide[p]]] > kWideSteps * L)
+                ++er_nwide[p];
+        const int64_t rest = (int64_t)er_rows[p].size() - er_nwide[p];
+        P->er_slice_start[p + 1] = P->er_slice_start[p] + er_nwide[p] + (int32_t)((rest + C - 1) / C);
+    }
     P->nparts = nparts;
     P->ner_slices = P->er_slice_start[nparts];
     P->er_row.assign((size_t)P->ner_slices * C, 0xFFFF);
-    for (int32_t p = 0; p < nparts; ++p)
-        for (size_t j = 0; j < er_rows[p].size(); ++j)
-            P->er_row[(size_t)P->er_slice_start[p] * C + j] = er_rows[p][j];
+    for (int32_t p = 0; p < nparts; ++p) {
+        const size_t e0 = (size_t)P->er_slice_start[p];
+        const int32_t nw = er_nwide[p];
+        for (int32_t j = 0; j < nw; ++j) P->er_row[(e0 + j) * C] = er_rows[p][j];
+        for (size_t j = nw; j < er_rows[p].size(); ++j) P->er_row[(e0 + nw) * C + (j - nw)] = er_rows[p][j];
+    }
     build_er_pos(*P);
     P->t_reorder = now_s() - t0;
     t0 = now_s();
@@ -481,22 +494,25 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     int64_t roff = 0;
     {
         std::vector<int32_t> er_steps(nes, 0);
+        std::vector<char> wide(nes, 0);
         for (int32_t p = 0; p < nparts; ++p) {
             const int32_t ps = P->part_start[p];
             for (int32_t e = P->er_slice_start[p]; e < P->er_slice_start[p + 1]; ++e) {
+                wide[e] = e - P->er_slice_start[p] < er_nwide[p];
                 int32_t mr = 0;
                 for (int32_t r = 0; r < C; ++r) {
                     const uint16_t lr = P->er_row[(size_t)e * C + r];
                     if (lr != 0xFFFF) mr = std::max(mr, P->row_er_len[ps + lr]);
                 }
-                er_steps[e] = (mr + L - 1) / L;
+                er_steps[e] = wide[e] ? (mr + kWave - 1) / kWave : (mr + L - 1) / L;
             }
         }
         for (int32_t e = 0; e < nes; ++e) {
             if (roff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the residual part");
             P->er_meta[2 * (size_t)e + 0] = (uint32_t)roff;
-            P->er_meta[2 * (size_t)e + 1] = (uint32_t)er_steps[e];
+            P->er_meta[2 * (size_t)e + 1] = (uint32_t)er_steps[e] | (wide[e] ? kErWide : 0u);
             roff += (int64_t)er_steps[e] * kWave;
+            P->n_er_wide += wide[e];
         }
     }
     if (roff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the residual part");
@@ -532,6 +548,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                 const int32_t ell_len = P->row_ell_len[row];
                 const int32_t ep = P->er_pos[row];
                 const int64_t ro = ep >= 0 ? (int64_t)P->er_meta[2 * (size_t)(ep / C)] : 0;
+                const bool ew = ep >= 0 && (P->er_meta[2 * (size_t)(ep / C) + 1] & kErWide);
                 const int32_t rr = ep >= 0 ? ep % C : 0;
                 const int32_t* hb = P->halo_idx.data() + P->halo_start[p];
                 const int32_t* he = P->halo_idx.data() + P->halo_start[p + 1];
@@ -551,7 +568,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                         P->ell_col[slot] = (uint16_t)local;
                         if (local >= pe - ps) ++nnz_halo;
                     } else {
-                        const int64_t slot = er_slot_of(ro, k2++, rr, L);
+                        const int64_t slot = ew ? er_slot_of(ro, k2++, 0, kWave) : er_slot_of(ro, k2++, rr, L);
                         store_value(&P->er_val[(size_t)slot * vb], vb, dt, v);
                         P->er_col[slot] = nc;
                     }
@@ -612,7 +629,7 @@ ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, c
         if (prm.imbalance_pct == 0) prm.imbalance_pct = 3;
         if (prm.imbalance_pct < 0 || prm.imbalance_pct > 100)
             return fail(EHYB_EINVAL, "imbalance_pct must be in [0, 100]");
-        if (prm.ell_width_cap < 0) return fail(EHYB_EINVAL, "ell_width_cap must be >= 0");
+        if (prm.ell_width_cap < -1) return fail(EHYB_EINVAL, "ell_width_cap must be >= -1");
         if (prm.partitioner < 0 || prm.partitioner > 1) return fail(EHYB_EINVAL, "unknown partitioner");
         if (prm.n_threads < 0) return fail(EHYB_EINVAL, "n_threads must be >= 0");
 
@@ -644,6 +661,11 @@ ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, c
             return fail(EHYB_EINVAL, "slice_rows exceeds the LDS budget (2 * x bytes per row) or 65535 rows");
         const int64_t cap = std::min<int64_t>(max_rows, prm.slice_rows + (int64_t)prm.slice_rows * prm.imbalance_pct / 100);
         const int32_t nparts_req = n > 0 ? (int32_t)((n + prm.slice_rows - 1) / prm.slice_rows) : 0;
+        // ELL width cap: -1 none (the paper's split), > 0 as given, 0 the
+        // automatic cap of kAutoCapSteps load steps per row-slice lane group
+        // (only hub rows reach it; their excess goes to wide residual slices)
+        if (prm.ell_width_cap == 0) prm.ell_width_cap = kAutoCapSteps * P->L * P->kc;
+        else if (prm.ell_width_cap < 0) prm.ell_width_cap = 0;
         P->params = prm;
         ThreadGuard tg(threads_for(prm));
 
@@ -737,6 +759,8 @@ ehyb_status ehyb_plan_stats_get(const ehyb_plan* P, ehyb_plan_stats* out) {
     out->ell_slots = P->ell_slots;
     out->er_slots = P->er_slots;
     out->n_er_rows = P->n_er_rows;
+    out->n_er_wide = P->n_er_wide;
+    out->ell_width_cap = P->params.ell_width_cap;
     out->nnz_halo = P->nnz_halo;
     out->n_halo = (int64_t)P->halo_idx.size();
     out->max_halo = P->max_halo;
@@ -812,10 +836,11 @@ ehyb_status ehyb_plan_decode_csr(const ehyb_plan* P, int64_t* row_ptr, int32_t* 
                 const int32_t na = P->row_ell_len[row], nb = P->row_er_len[row];
                 const int32_t ep = P->er_pos[row];
                 const int64_t ro = ep >= 0 ? (int64_t)P->er_meta[2 * (size_t)(ep / C)] : 0;
+                const bool ew = ep >= 0 && (P->er_meta[2 * (size_t)(ep / C) + 1] & kErWide);
                 const int32_t rr = ep >= 0 ? ep % C : 0;
                 while (a < na || b < nb) {
                     const int64_t sa = a < na ? ell_slot_of(eo, a, r, L, kc) : 0;
-                    const int64_t sb = b < nb ? er_slot_of(ro, b, rr, L) : 0;
+                    const int64_t sb = b < nb ? (ew ? er_slot_of(ro, b, 0, kWave) : er_slot_of(ro, b, rr, L)) : 0;
                     int32_t ca = INT32_MAX;
                     if (a < na) {
                         const int32_t lc = P->ell_col[sa];
@@ -944,7 +969,7 @@ const char* validate_loaded(const ehyb_plan& P) {
         const int64_t sz = (int64_t)P.part_start[p + 1] - P.part_start[p];
         const int64_t sl = (int64_t)P.slice_start[p + 1] - P.slice_start[p];
         const int64_t el = (int64_t)P.er_slice_start[p + 1] - P.er_slice_start[p];
-        if (sz <= 0 || sz > max_rows || sl != (sz + C - 1) / C || el < 0 || el > sl)
+        if (sz <= 0 || sz > max_rows || sl != (sz + C - 1) / C || el < 0 || el > sz)
             return "plan file partition sizes are inconsistent";
         if (P.ell_free[p] < 0 || P.ell_free[p] > sl) return "plan file ELL free-slice count is inconsistent";
         std::vector<char> seen_j((size_t)sl, 0);
@@ -962,11 +987,14 @@ const char* validate_loaded(const ehyb_plan& P) {
             if (rows < 64 && (mask >> rows) != 0) return "plan file residual mask names a missing row";
         }
         for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e) {
-            const uint64_t ro = P.er_meta[2 * (size_t)e], rs = P.er_meta[2 * (size_t)e + 1];
+            const uint64_t ro = P.er_meta[2 * (size_t)e], rs = P.er_meta[2 * (size_t)e + 1] & ~kErWide;
+            const bool wide = (P.er_meta[2 * (size_t)e + 1] & kErWide) != 0;
             if (ro + rs * kWave > (uint64_t)P.er_slots) return "plan file residual slot range out of bounds";
+            if (wide && C == 1) return "plan file has a wide residual slice with one row per slice";
             for (int r = 0; r < C; ++r) {
                 const uint16_t lr = P.er_row[(size_t)e * C + r];
                 if (lr != 0xFFFF && lr >= sz) return "plan file residual row outside its partition";
+                if (wide && (r == 0) != (lr != 0xFFFF)) return "plan file wide residual slice must hold one row";
             }
         }
     }
@@ -1114,6 +1142,8 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         P->iperm.resize((size_t)P->n);
         for (size_t i = 0; i < (size_t)P->n; ++i) P->iperm[P->perm[i]] = (int32_t)i;
         build_er_pos(*P);
+        P->n_er_wide = 0;
+        for (int32_t e = 0; e < P->ner_slices; ++e) P->n_er_wide += (P->er_meta[2 * (size_t)e + 1] & kErWide) != 0;
         *out = P.release();
         return EHYB_OK;
     } catch (const std::bad_alloc&) {

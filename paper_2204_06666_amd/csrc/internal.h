@@ -18,6 +18,14 @@ constexpr int kWave = 64;              // gfx950 wavefront width
 constexpr int kc_for(int value_dtype) { return value_dtype == EHYB_F64 ? 2 : (value_dtype == EHYB_F32 ? 4 : 8); }
 constexpr size_t kBlobAlign = 256;
 constexpr int kStaticLds = 64;         // LDS the SpMV kernel keeps for its queue counters
+// A residual row that would need more than kWideSteps load steps on its L
+// lanes gets a residual slice of its own, processed by all 64 lanes of a
+// wavefront ("wide" slice, flagged by bit 31 of its step count).
+constexpr int kWideSteps = 32;
+// The automatic ELL width cap: a row-slice lane group loads at most this many
+// steps of one row (256 FP64 entries per lane at one lane per row).
+constexpr int kAutoCapSteps = 128;
+constexpr uint32_t kErWide = 1u << 31;
 
 // Allocator whose resize() leaves new elements uninitialised, so that large
 // arrays filled by parallel loops are not first zeroed by one thread.
@@ -105,6 +113,7 @@ struct ehyb_plan {
     std::vector<int32_t> row_ell_len, row_er_len;  // [n], permuted rows
     int64_t ell_slots = 0, er_slots = 0;
     int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0, nnz_halo = 0;
+    int32_t n_er_wide = 0;                // residual slices processed by all 64 lanes
     int32_t max_halo = 0;
     double t_graph = 0, t_partition = 0, t_reorder = 0, t_encode = 0;
     int32_t n_rhs = 1;             // right-hand sides the LDS budget is sized for

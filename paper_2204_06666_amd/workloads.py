@@ -28,7 +28,7 @@ HEADLINE_PARAMS = {
 
 # The paper's split: every entry outside the partition goes to the residual
 # part and reads x from device memory.
-PAPER_SPLIT_PARAMS = dict(HEADLINE_PARAMS, halo_rows=-1)
+PAPER_SPLIT_PARAMS = dict(HEADLINE_PARAMS, halo_rows=-1, ell_width_cap=-1)
 
 # the batched product (64 uneven FP32 matrices x 8 right-hand sides): plans
 # within half the LDS, so that two workgroups share a CU

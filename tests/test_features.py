@@ -92,7 +92,7 @@ def test_reencode_with_given_partition():
         P = Plan(A, partition=part, **kw)
         assert np.array_equal(P.partition(), part), kw
         check_plan(A, P.arrays(), x_bytes=8 if kw.get("value_dtype", 0) == 0 else 4,
-                   width_cap=kw.get("ell_width_cap", 0),
+                   width_cap=P.stats()["ell_width_cap"],
                    value_dtype=np.float64 if kw.get("value_dtype", 0) == 0 else np.float32)
         assert P.stats()["slice_rows"] == np.bincount(part).max()
 

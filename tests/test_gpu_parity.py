@@ -86,6 +86,18 @@ def test_matrix_families(torch, name, make, kw, rpw, halo):
     _check(A, x, y, f"{name} rpw={rpw} halo={halo} parts={st['nparts']} er={st['nnz_er']}")
 
 
+@pytest.mark.parametrize("rpw,halo,cap", [(64, -1, 0), (8, -1, 0), (16, 0, 40), (64, 0, 30)])
+def test_hub_rows_in_wide_residual_slices(torch, rpw, halo, cap):
+    """Power-law matrix with hub rows of thousands of entries: residual rows
+    longer than 32 * L entries run on all 64 lanes (wide slices)."""
+    A = matgen.powerlaw(40000, exponent=2.1, mean_deg=20, seed=17)
+    x = matgen.uniform_vector(A.n_rows, 18)
+    y, P = _ehyb(torch, A, x, rows_per_wave=rpw, halo_rows=halo, ell_width_cap=cap, slice_rows=2000)
+    st = P.stats()
+    assert st["n_er_wide"] > 0
+    _check(A, x, y, f"hub rows rpw={rpw} halo={halo} cap={cap} wide={st['n_er_wide']}")
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 129])
 def test_tiny_ragged(torch, n):
     A = matgen.random_small(n, 0.4, n + 3, empty_rows=min(2, n - 1))

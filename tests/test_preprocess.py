@@ -13,7 +13,9 @@ from oracle.structure import check_plan, layout_spmv
 from paper_2204_06666_amd import EhybError, Plan, _abi
 
 
-def _full_check(A, plan, value_dtype=np.float64, width_cap=0, x_seed=7, x_bytes=8):
+def _full_check(A, plan, value_dtype=np.float64, width_cap=None, x_seed=7, x_bytes=8):
+    if width_cap is None:
+        width_cap = plan.stats()["ell_width_cap"]      # the cap in effect (automatic by default)
     v = plan.arrays()
     st = check_plan(A, v, width_cap=width_cap, value_dtype=value_dtype, x_bytes=x_bytes)
     perm = v["perm"]
@@ -307,3 +309,28 @@ def test_lds_budget_respected_at_the_limit(sr):
     P = Plan(A, slice_rows=min(sr, A.n_rows))
     s = P.stats()
     assert s["lds_bytes_used"] <= 160 * 1024 - 64
+
+
+def test_automatic_width_cap_sends_hub_rows_to_wide_slices():
+    """Default plans cap ELL rows at 128 load steps per lane group: only hub
+    rows reach it, and their excess runs on wide residual slices; -1 keeps
+    the paper's uncapped split."""
+    A = matgen.powerlaw(20000, exponent=2.1, mean_deg=20, seed=17)
+    lens = np.diff(A.row_ptr)
+    for rpw in (64, 8):
+        P = Plan(A, slice_rows=2000, rows_per_wave=rpw)
+        st = P.stats()
+        cap = 128 * (64 // rpw) * 2
+        assert st["ell_width_cap"] == cap
+        assert lens.max() > cap and st["n_er_wide"] > 0
+        arr = P.arrays()
+        assert arr["row_ell_len"].max() == cap
+        _full_check(A, P)
+    Q = Plan(A, slice_rows=2000, ell_width_cap=-1)
+    assert Q.stats()["ell_width_cap"] == 0
+    _full_check(A, Q, width_cap=0)
+    # regular matrices never reach the automatic cap: same plan as uncapped
+    B = matgen.stencil3d(14, perm_seed=1, val_seed=2)
+    a1, a2 = Plan(B, slice_rows=800).arrays(), Plan(B, slice_rows=800, ell_width_cap=-1).arrays()
+    for k in ("perm", "ell_val", "ell_col", "er_col"):
+        assert np.array_equal(a1[k], a2[k]), k

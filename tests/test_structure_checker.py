@@ -95,3 +95,43 @@ def test_lds_budget_and_16bit_limit():
     A, _, view = _tiny()
     with pytest.raises(PlanError, match="on-chip"):
         check_plan(A, view, x_bytes=8, lds_budget=8)
+
+
+def _wide_view():
+    """A power-law plan with the paper's split (no halo): hub rows have more
+    than 32 residual entries and get wide residual slices."""
+    from paper_2204_06666_amd import Plan
+    A = matgen.powerlaw(3000, exponent=2.3, mean_deg=12, seed=9)
+    P = Plan(A, slice_rows=400, halo_rows=-1)
+    arr = P.arrays()
+    view = {k: (np.array(v, copy=True) if isinstance(v, np.ndarray) else v) for k, v in arr.items()}
+    view["er_meta"] = view["er_meta"].reshape(-1, 2)
+    view["er_row"] = view["er_row"].reshape(-1, 64 // view["L"])
+    return A, view
+
+
+def test_wide_residual_slices_pass_and_interpret():
+    A, view = _wide_view()
+    st = check_plan(A, view)
+    assert st["n_er_wide"] > 0
+    x = matgen.uniform_vector(A.n_rows, 4)
+    perm = np.asarray(view["perm"])
+    import oracle
+    yp = layout_spmv(view, x[perm])
+    y = np.empty_like(yp)
+    y[perm] = yp
+    oracle.assert_close(y, oracle.spmv(A, x), oracle.abs_scale(A, x), 1e-12, "wide slices")
+
+
+def test_wide_slice_mistakes_are_caught():
+    A, view = _wide_view()
+    wide = np.nonzero(view["er_meta"][:, 1] & (1 << 31))[0]
+    normal = np.nonzero((view["er_meta"][:, 1] & (1 << 31)) == 0)[0]
+    v1 = {k: (a.copy() if isinstance(a, np.ndarray) else a) for k, a in view.items()}
+    v1["er_meta"][wide[0], 1] &= np.uint32(0x7FFFFFFF)  # a long row left to one lane group
+    with pytest.raises(PlanError):
+        check_plan(A, v1)
+    v2 = {k: (a.copy() if isinstance(a, np.ndarray) else a) for k, a in view.items()}
+    v2["er_meta"][normal[-1], 1] |= np.uint32(1 << 31)  # a short-row slice flagged wide
+    with pytest.raises(PlanError):
+        check_plan(A, v2)
