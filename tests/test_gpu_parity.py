@@ -98,6 +98,30 @@ def test_hub_rows_in_wide_residual_slices(torch, rpw, halo, cap):
     _check(A, x, y, f"hub rows rpw={rpw} halo={halo} cap={cap} wide={st['n_er_wide']}")
 
 
+@pytest.mark.parametrize("value_dtype,rows,side", [(0, (160 * 1024 - 64) // 16, 36), (1, (160 * 1024 - 64) // 8, 34)])
+def test_largest_partitions(torch, value_dtype, rows, side):
+    """Partitions at the LDS limit (x-slice and residual accumulators fill
+    the 160 KiB)."""
+    A = matgen.stencil3d(side, perm_seed=3, val_seed=4)
+    P = Plan(A, slice_rows=rows, imbalance_pct=0, value_dtype=value_dtype).upload("cuda:0")
+    st = P.stats()
+    assert st["max_part_rows"] <= rows and st["lds_bytes_used"] <= 160 * 1024 - 64
+    assert st["max_part_rows"] > 0.9 * rows
+    x = matgen.uniform_vector(A.n_rows, 8)
+    xd = _dev(torch, x[P.perm()].astype(np.float64 if value_dtype == 0 else np.float32))
+    yp = P.spmv(xd).cpu().numpy().astype(np.float64)
+    y = np.empty_like(yp)
+    y[P.perm()] = yp
+    if value_dtype == 0:
+        _check(A, x, y, f"largest partitions ({st['max_part_rows']} rows)")
+    else:
+        from oracle.precision import gamma32, quantize
+        Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, "f32"))
+        xq = x.astype(np.float32).astype(np.float64)
+        ref, sc = oracle.spmv(Aq, xq), oracle.abs_scale(Aq, xq)
+        assert np.all(np.abs(y - ref) <= gamma32(np.diff(A.row_ptr) + 2) * sc)
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 129])
 def test_tiny_ragged(torch, n):
     A = matgen.random_small(n, 0.4, n + 3, empty_rows=min(2, n - 1))
