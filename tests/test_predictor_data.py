@@ -47,3 +47,26 @@ def test_model_file():
     n = len(load_sweeps([SWEEP]))
     assert 0 < m["n_train"] < n and m["n_held_out"] == n - m["n_train"]
     assert m["result"]["held_out"]["n"] == n - m["n_train"]
+
+
+def test_recorded_result_meets_the_targets():
+    """The held-out result stored with the committed model meets the targets
+    (within 10% of the exhaustive best, geomean; faster than the Eq. 1
+    default), and recomputing it on the CPU (FP64 reference network on the
+    stored weights, committed sweep times) gives the same figures."""
+    if not os.path.exists(MODEL):
+        pytest.skip("no committed model")
+    from oracle import mlp
+    from paper_2204_06666_amd.predictor import decode_output
+    from paper_2204_06666_amd.train_predictor import Predictor, evaluate
+    d = json.load(open(MODEL))
+    res = d["meta"]["result"]["held_out"]
+    assert res["geomean_pred_over_best"] <= 1.10
+    assert res["share_pred_within_1.10"] >= 0.7
+    assert res["geomean_eq1_over_pred"] > 1.0
+    pred = Predictor.load(MODEL)
+    te = [r for r in load_sweeps([SWEEP]) if r["i"] >= d["meta"]["n_train"]]
+    Y, _ = mlp.forward(pred.params.astype(np.float64), pred.normalise([r["features"] for r in te]).astype(np.float64))
+    again = evaluate(te, [decode_output(y) for y in Y])
+    assert abs(again["geomean_pred_over_best"] - res["geomean_pred_over_best"]) <= 0.01
+    assert abs(again["geomean_eq1_over_pred"] - res["geomean_eq1_over_pred"]) <= 0.02
