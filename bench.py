@@ -91,11 +91,10 @@ def main():
                          "uneven FP32 matrices x 8 right-hand sides in one launch; predictor: the "
                          "learned preprocessing parameters on held-out matrices")
     ap.add_argument("--count", type=int, default=64, help="batched only: number of matrices")
-    ap.add_argument("--lds-bytes", type=int, default=80 * 1024,
-                    help="batched only: LDS budget per partition (80 KiB lets two workgroups share a "
-                         "CU; 0 = 160 KiB)")
-    ap.add_argument("--halo-rows", type=int, default=0, help="batched only: halo_rows of the plans")
-    ap.add_argument("--rows-per-wave", type=int, default=64, help="batched only: rows_per_wave (64, 16 or 4)")
+    ap.add_argument("--lds-bytes", type=int, default=None,
+                    help="batched only: LDS budget per partition (default: the autotuner's choice)")
+    ap.add_argument("--halo-rows", type=int, default=None, help="batched only: halo_rows of the plans")
+    ap.add_argument("--rows-per-wave", type=int, default=None, help="batched only: rows_per_wave (64, 16 or 4)")
     ap.add_argument("--live", type=int, default=16, help="predictor only: held-out matrices re-timed live")
     ap.add_argument("--scale", type=float, default=1.0,
                     help="knn-fem only: fraction of the 1e6 points")
@@ -363,6 +362,13 @@ def run_batched(args):
 
     nrhs = 8
     dev = torch.device("cuda:0")
+    # plan parameters: the committed batch autotuning result, unless given
+    from paper_2204_06666_amd.workloads import BATCHED_PARAMS, batched_tuned
+    tuned = batched_tuned() or BATCHED_PARAMS
+    for k in ("lds_bytes", "halo_rows", "rows_per_wave"):
+        if getattr(args, k) is None:
+            setattr(args, k, tuned[k])
+    log(f"plan parameters {dict(lds_bytes=args.lds_bytes, halo_rows=args.halo_rows, rows_per_wave=args.rows_per_wave)}")
     log(f"generating {args.count} matrices")
     mats = []
     for i, fm in enumerate(matgen.batch_matrices(args.count)):
@@ -478,7 +484,9 @@ def run_batched(args):
         "config": {"workload": f"{args.count} matrices, n log-uniform in [1e4, 5e5], 2-D Poisson / "
                                f"27-point stencil / kNN-FEM 3 dof (seeds 4000+i), 8 RHS ~ U[-1,1], FP32",
                    "plan": {"lds_bytes": args.lds_bytes or 160 * 1024, "halo_rows": args.halo_rows,
-                            "rows_per_wave": args.rows_per_wave},
+                            "rows_per_wave": args.rows_per_wave,
+                            "source": "autotuner (paper_2204_06666_amd/data/batched_tuning.json)"
+                            if batched_tuned() else "default"},
                    "sum_n": sum_n, "sum_nnz": sum_nnz, "work_items": sum(p.stats()["nparts"] for p in plans)},
         "roofline": {"bound": "hbm", "achieved": round(algo / kern_g / 1e9, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(algo / kern_g / 1e9 / PEAK_HBM_GBPS, 4),

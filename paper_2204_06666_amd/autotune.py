@@ -95,6 +95,49 @@ def best_point(rec: dict):
     return min(grid_points(rec), key=lambda g: g[3])
 
 
+# the batched product: launch shape and plan parameters shared by the batch
+BATCH_GRID = {"lds_bytes": (40 * 1024, 54 * 1024, 80 * 1024, 160 * 1024), "rows_per_wave": (64, 16),
+              "halo_rows": (0, -1)}
+
+
+def tune_batch(mats, n_rhs: int = 8, device="cuda:0", launches: int = 20, rounds: int = 3, log=None) -> dict:
+    """Exhaustive tuning of the batched product (FP32 values): every point of
+    BATCH_GRID builds the batch's plans and times one launch over all of
+    them.  Returns {"best": params, "points": [[params, us], ...]}."""
+    import itertools
+
+    import torch
+
+    from . import Batch
+    g = np.random.Generator(np.random.PCG64(4999))
+    X0 = [g.uniform(-1.0, 1.0, (A.n_rows, n_rhs)).astype(np.float32) for A in mats]
+    points = []
+    keys = list(BATCH_GRID)
+    for combo in itertools.product(*(BATCH_GRID[k] for k in keys)):
+        prm = dict(zip(keys, combo))
+        plans = [Plan(A, value_dtype=EHYB_F32, n_rhs=n_rhs, **prm).upload(device) for A in mats]
+        B = Batch(plans, n_rhs, device)
+        Xd = [torch.from_numpy(x[p.perm()]).to(device) for x, p in zip(X0, plans)]
+        Yd = [torch.empty_like(x) for x in Xd]
+        B.spmm(Xd, Yd)
+        torch.cuda.synchronize()
+        best = float("inf")
+        for _ in range(rounds):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(launches):
+                B.spmm(Xd, Yd)
+            e1.record()
+            torch.cuda.synchronize()
+            best = min(best, e0.elapsed_time(e1) * 1e3 / launches)
+        points.append([prm, round(best, 2)])
+        if log:
+            log(f"batch point {prm}: {best:.1f} us")
+        del B, plans, Xd, Yd
+    best = min(points, key=lambda q: q[1])
+    return {"n_rhs": n_rhs, "best": best[0], "best_us": best[1], "points": points}
+
+
 def main(argv=None):
     import matgen
 
@@ -104,7 +147,15 @@ def main(argv=None):
     ap.add_argument("--n-lo", type=int, default=10_000)
     ap.add_argument("--n-hi", type=int, default=250_000)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--batch", action="store_true",
+                    help="tune the batched product of the 64-matrix batch instead (writes JSON)")
     args = ap.parse_args(argv)
+    if args.batch:
+        mats = [A for _, A in matgen.batch_matrices(64)]
+        res = tune_batch(mats, log=lambda m: print(f"[autotune] {m}", flush=True))
+        json.dump(res, open(args.out, "w"), indent=1)
+        print(f"[autotune] batch best {res['best']} {res['best_us']} us", flush=True)
+        return 0
     with open(args.out, "a") as f:
         for i in range(args.start, args.start + args.count):
             t0 = time.perf_counter()

@@ -40,10 +40,11 @@ def main():
         run = lambda: plan.spmv(xp, yp)  # noqa: E731
     else:
         from paper_2204_06666_amd import EHYB_F32, Batch
-        from paper_2204_06666_amd.workloads import BATCHED_PARAMS
-        nrhs = BATCHED_PARAMS["n_rhs"]
+        from paper_2204_06666_amd.workloads import BATCHED_PARAMS, batched_tuned
+        prm = batched_tuned() or BATCHED_PARAMS
+        nrhs = prm["n_rhs"]
         mats = [A for _, A in matgen.batch_matrices(64)]
-        plans = [Plan(A, value_dtype=EHYB_F32, **BATCHED_PARAMS).upload(dev) for A in mats]
+        plans = [Plan(A, value_dtype=EHYB_F32, **prm).upload(dev) for A in mats]
         batch = Batch(plans, nrhs, dev)
         g = matgen.rng(4999)
         Xd = [torch.from_numpy(g.uniform(-1, 1, (A.n_rows, nrhs)).astype("float32")).to(dev) for A in mats]

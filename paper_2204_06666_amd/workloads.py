@@ -33,3 +33,15 @@ PAPER_SPLIT_PARAMS = dict(HEADLINE_PARAMS, halo_rows=-1, ell_width_cap=-1)
 # the batched product (64 uneven FP32 matrices x 8 right-hand sides): plans
 # within half the LDS, so that two workgroups share a CU
 BATCHED_PARAMS = dict(n_rhs=8, lds_bytes=80 * 1024, halo_rows=0, rows_per_wave=64)
+
+
+def batched_tuned():
+    """Plan parameters the batch autotuner chose (committed result), or None."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "batched_tuning.json")
+    try:
+        best = json.load(open(path))["best"]
+    except (OSError, ValueError, KeyError):
+        return None
+    return dict(n_rhs=8, **best)

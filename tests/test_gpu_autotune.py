@@ -53,3 +53,14 @@ def test_predictor_learns_a_rule():
     print(f"[predictor] synthetic held-out: {res}", flush=True)
     assert hist[-1] < 0.2 * hist[0]
     assert res["share_pred_within_1.10"] >= 0.8
+
+
+def test_batch_tuner_on_a_small_batch():
+    from paper_2204_06666_amd.autotune import BATCH_GRID, tune_batch
+    mats = [matgen.stencil3d(10, perm_seed=i, val_seed=i) for i in range(3)] + [matgen.knn_fem(400, perm_seed=5)]
+    res = tune_batch(mats, n_rhs=8, launches=2, rounds=1)
+    n = 1
+    for v in BATCH_GRID.values():
+        n *= len(v)
+    assert len(res["points"]) == n and res["best_us"] == min(t for _, t in res["points"])
+    assert set(res["best"]) == set(BATCH_GRID)
