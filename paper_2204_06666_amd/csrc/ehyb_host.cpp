@@ -914,7 +914,7 @@ struct Reader {
             ok = false;
             return;
         }
-        std::memcpy(d, p + at, k);
+        if (k) std::memcpy(d, p + at, k);  // an empty vector's data() may be null
         at += k;
     }
     template <class T> void pod(T& v) { raw(&v, sizeof(T)); }
