@@ -293,7 +293,7 @@ def run_precision(args):
     import matgen
     import oracle
     from oracle.precision import quantize
-    from paper_2204_06666_amd import EHYB_BF16, EHYB_F32, EHYB_F64, Plan
+    from paper_2204_06666_amd import EHYB_BF16, EHYB_BF16_ACC64, EHYB_F32, EHYB_F32_ACC64, EHYB_F64, Plan
 
     dev = torch.device("cuda:0")
     log(f"generating the kNN-FEM matrix (scale {args.scale})")
@@ -305,7 +305,8 @@ def run_precision(args):
     y64 = oracle.spmv(A, x)
     s64 = oracle.abs_scale(A, x)
     res = {}
-    for name, dt in (("f64", EHYB_F64), ("f32", EHYB_F32), ("bf16", EHYB_BF16)):
+    for name, dt in (("f64", EHYB_F64), ("f32", EHYB_F32), ("bf16", EHYB_BF16), ("f32_acc64", EHYB_F32_ACC64),
+                     ("bf16_acc64", EHYB_BF16_ACC64)):
         log(f"preprocessing {name}")
         t0 = time.perf_counter()
         plan = Plan(A, value_dtype=dt).upload(dev)
@@ -328,7 +329,7 @@ def run_precision(args):
                      "nparts": st["nparts"], "nnz_er": st["nnz_er"], "nnz_halo": st["nnz_halo"],
                      "preprocess_s": round(t_pre, 2)}
         if dt != EHYB_F64:
-            Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, name))
+            Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, name.split("_")[0]))
             xq = x.astype(np.float32).astype(np.float64)
             eq = oracle.scaled_error(y, oracle.spmv(Aq, xq), oracle.abs_scale(Aq, xq))
             res[name]["max_row_scaled_error_vs_quantized"] = float(eq.max())

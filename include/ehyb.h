@@ -55,8 +55,14 @@ typedef enum {
     EHYB_ESTATE = -5         /* call out of order (e.g. spmv before upload) */
 } ehyb_status;
 
-/* Storage type of matrix values.  EHYB_F64: FP64 values, FP64 x/y/accumulate. */
-typedef enum { EHYB_F64 = 0, EHYB_F32 = 1, EHYB_BF16 = 2 } ehyb_dtype;
+/* Value type of a plan.  EHYB_F64: FP64 values, FP64 x/y/accumulation.
+ * EHYB_F32 / EHYB_BF16: binary32 / bfloat16 values (rounded to nearest even
+ * from the FP64 input), binary32 x and y, binary32 accumulation.
+ * EHYB_F32_ACC64 / EHYB_BF16_ACC64: the same values and x, binary64
+ * accumulation (each product and sum in FP64, y rounded to binary32 once):
+ * for long rows, where binary32 accumulation error grows with the row
+ * length.  Their residual accumulators take 8 bytes of LDS per row. */
+typedef enum { EHYB_F64 = 0, EHYB_F32 = 1, EHYB_BF16 = 2, EHYB_F32_ACC64 = 3, EHYB_BF16_ACC64 = 4 } ehyb_dtype;
 
 /* Which partitioner builds the partitions (Section 3.1 asks for a graph
  * partitioner minimising the entries that fall outside their row's

@@ -160,8 +160,9 @@ def layout_entries(view):
 
 
 def stored_values_f64(view, vals) -> np.ndarray:
-    """Stored values as float64 (bfloat16 plans keep bit patterns)."""
-    if int(view.get("value_dtype", 0)) == 2:
+    """Stored values as float64 (bfloat16 plans keep bit patterns; value
+    types 2 and 4 store bfloat16, 1 and 3 binary32, 0 binary64)."""
+    if int(view.get("value_dtype", 0)) in (2, 4):
         from .precision import bf16_bits_to_f64
         return bf16_bits_to_f64(vals)
     return np.asarray(vals).astype(np.float64)
@@ -176,12 +177,13 @@ def layout_spmv(view, xp: np.ndarray) -> np.ndarray:
 
 
 def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_cap: int = 0,
-               value_dtype=np.float64, Bperm=None) -> dict:
+               value_dtype=np.float64, Bperm=None, acc_bytes: int | None = None) -> dict:
     """Check every structural property of an EHYB encoding of ``A``.
 
     ``value_dtype`` is the storage type of values (float64 plans must reproduce
     A's bits; float32 and "bf16" plans must reproduce A's values rounded to
-    nearest-even in that type).  ``Bperm`` may pass a precomputed P A P^T.  Returns statistics."""
+    nearest-even in that type).  ``acc_bytes`` is the size of a residual
+    accumulator in LDS (default x_bytes; 8 for binary64 accumulation).  ``Bperm`` may pass a precomputed P A P^T.  Returns statistics."""
     from . import permute
 
     n = int(view["n"])
@@ -211,7 +213,9 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
     _req((np.diff(halo_idx)[inner] > 0).all(), "halo not strictly ascending")
     _req((sizes + hsz <= 65535).all(), "LDS vector larger than a 16-bit local index allows")
     has_er = int(np.asarray(view["er_meta"]).size) > 0
-    lds = (sizes.max(initial=0) + hsz.max(initial=0) + (sizes.max(initial=0) if has_er else 0)) * x_bytes
+    ab = x_bytes if acc_bytes is None else acc_bytes       # bytes of one residual accumulator
+    xs_bytes = (sizes.max(initial=0) + hsz.max(initial=0)) * x_bytes
+    lds = (-(-xs_bytes // ab) * ab + sizes.max(initial=0) * ab) if has_er else xs_bytes
     _req(lds <= lds_budget, "x-slice, halo and residual accumulators exceed the on-chip budget")
 
     L = int(view["L"])

@@ -17,15 +17,18 @@ from typing import Optional
 import numpy as np
 
 from . import _abi
-from ._abi import (EHYB_BF16, EHYB_F32, EHYB_F64, EHYB_LOAD_AUTO, EHYB_LOAD_CACHED,  # noqa: F401
+from ._abi import (EHYB_BF16, EHYB_BF16_ACC64, EHYB_F32, EHYB_F32_ACC64, EHYB_F64,  # noqa: F401
+                   EHYB_LOAD_AUTO, EHYB_LOAD_CACHED,
                    EHYB_LOAD_STREAM, EHYB_VEC_PERMUTED, EhybError,
                    check, load)
 
 __all__ = ["Plan", "Batch", "csr_spmv", "probe_read", "probe_copy", "device_info", "version",
-           "EhybError", "EHYB_F64", "EHYB_F32", "EHYB_BF16", "EHYB_VEC_PERMUTED", "EHYB_LOAD_AUTO",
+           "EhybError", "EHYB_F64", "EHYB_F32", "EHYB_BF16", "EHYB_F32_ACC64", "EHYB_BF16_ACC64",
+           "EHYB_VEC_PERMUTED", "EHYB_LOAD_AUTO",
            "EHYB_LOAD_CACHED", "EHYB_LOAD_STREAM", "load"]
 
-_NP_VAL = {EHYB_F64: np.float64, EHYB_F32: np.float32, EHYB_BF16: np.uint16}
+_NP_VAL = {EHYB_F64: np.float64, EHYB_F32: np.float32, EHYB_BF16: np.uint16,
+           EHYB_F32_ACC64: np.float32, EHYB_BF16_ACC64: np.uint16}
 
 
 def version() -> str:

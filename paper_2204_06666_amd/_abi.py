@@ -13,7 +13,7 @@ c_vp, c_size = ctypes.c_void_p, ctypes.c_size_t
 EHYB_OK, EHYB_EINVAL, EHYB_ENOMEM, EHYB_EUNSUPPORTED, EHYB_EDEVICE, EHYB_ESTATE = 0, -1, -2, -3, -4, -5
 STATUS_NAMES = {0: "EHYB_OK", -1: "EHYB_EINVAL", -2: "EHYB_ENOMEM", -3: "EHYB_EUNSUPPORTED",
                 -4: "EHYB_EDEVICE", -5: "EHYB_ESTATE"}
-EHYB_F64, EHYB_F32, EHYB_BF16 = 0, 1, 2
+EHYB_F64, EHYB_F32, EHYB_BF16, EHYB_F32_ACC64, EHYB_BF16_ACC64 = 0, 1, 2, 3, 4
 EHYB_VEC_PERMUTED = 1
 EHYB_LOAD_AUTO, EHYB_LOAD_CACHED, EHYB_LOAD_STREAM = 0, 1, 2
 

@@ -141,6 +141,24 @@ template <> struct Prec<EHYB_BF16> {
     __device__ static __forceinline__ A value(V v) { return __uint_as_float((uint32_t)v << 16); }
 };
 
+// binary32 or bfloat16 values and binary32 x with binary64 accumulation:
+// the stored values widen exactly, every product and sum is FP64, and y is
+// rounded to binary32 once.
+template <int BASE> struct PrecAcc64 : Prec<BASE> {
+    using B = Prec<BASE>;
+    using A = double;
+    __device__ static __forceinline__ void unpack(const typename B::VL& v, typename B::CL c, A (&val)[B::KC],
+                                                  uint32_t (&col)[B::KC]) {
+        float f[B::KC];
+        B::unpack(v, c, f, col);
+#pragma unroll
+        for (int k = 0; k < B::KC; ++k) val[k] = (double)f[k];
+    }
+    __device__ static __forceinline__ A value(typename B::V v) { return (double)B::value(v); }
+};
+template <> struct Prec<EHYB_F32_ACC64> : PrecAcc64<EHYB_F32> {};
+template <> struct Prec<EHYB_BF16_ACC64> : PrecAcc64<EHYB_BF16> {};
+
 // NRHS consecutive elements (one row of a row-major multi-vector).
 template <class T, int N> struct Row {
     typedef T type __attribute__((ext_vector_type(N)));
@@ -268,7 +286,9 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
     constexpr int XV = 16 / (int)sizeof(X);  // x elements per 16-byte load
     constexpr int C = kWave / L;
     X* xs = reinterpret_cast<X*>(lds_raw);
-    Acc* yer = reinterpret_cast<Acc*>(xs + (size_t)a.lds_rows * NRHS);
+    // residual accumulators after the x-slice and halo, aligned to their size
+    const size_t yer_off = ((size_t)a.lds_rows * NRHS * sizeof(X) + sizeof(Acc) - 1) / sizeof(Acc) * sizeof(Acc);
+    Acc* yer = reinterpret_cast<Acc*>(lds_raw + yer_off);
     const int ps = a.part_start[p];
     const int sz = a.part_start[p + 1] - ps;
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -831,6 +851,8 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
         case EHYB_F64: ok = launch_spmv_dt<EHYB_F64>(P->L, nt, a, nblocks, threads, lds, s); break;
         case EHYB_F32: ok = launch_spmv_dt<EHYB_F32>(P->L, nt, a, nblocks, threads, lds, s); break;
         case EHYB_BF16: ok = launch_spmv_dt<EHYB_BF16>(P->L, nt, a, nblocks, threads, lds, s); break;
+        case EHYB_F32_ACC64: ok = launch_spmv_dt<EHYB_F32_ACC64>(P->L, nt, a, nblocks, threads, lds, s); break;
+        case EHYB_BF16_ACC64: ok = launch_spmv_dt<EHYB_BF16_ACC64>(P->L, nt, a, nblocks, threads, lds, s); break;
         default: break;
     }
     if (!ok) return fail(EHYB_EINVAL, "bad lanes per row or value type");
@@ -976,6 +998,12 @@ ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* co
         case EHYB_F64: ok = launch_batched_dt<EHYB_F64>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
         case EHYB_F32: ok = launch_batched_dt<EHYB_F32>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
         case EHYB_BF16: ok = launch_batched_dt<EHYB_BF16>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
+        case EHYB_F32_ACC64:
+            ok = launch_batched_dt<EHYB_F32_ACC64>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s);
+            break;
+        case EHYB_BF16_ACC64:
+            ok = launch_batched_dt<EHYB_BF16_ACC64>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s);
+            break;
         default: break;
     }
     if (!ok) return fail(EHYB_EUNSUPPORTED, "no batched kernel for this value type, rows_per_wave and n_rhs");

@@ -58,6 +58,7 @@ uint16_t double_to_bf16(double d) {
 }
 
 void store_value(unsigned char* dst, int vbytes, int dtype, double v) {
+    dtype = storage_dtype(dtype);
     if (dtype == EHYB_F64) {
         std::memcpy(dst, &v, 8);
     } else if (dtype == EHYB_F32) {
@@ -71,6 +72,7 @@ void store_value(unsigned char* dst, int vbytes, int dtype, double v) {
 }
 
 double load_value(const unsigned char* src, int dtype) {
+    dtype = storage_dtype(dtype);
     if (dtype == EHYB_F64) {
         double d;
         std::memcpy(&d, src, 8);
@@ -259,8 +261,11 @@ BlobLayout compute_layout(const ehyb_plan& p) {
 // LDS of one workgroup: x-slice + halo, then one residual accumulator per
 // row when the plan has residual entries, each n_rhs elements wide.
 int64_t lds_bytes_used(const ehyb_plan& p, int n_rhs) {
-    const int64_t rows = (int64_t)p.max_part_rows + p.max_halo + (p.ner_slices > 0 ? p.max_part_rows : 0);
-    return rows * p.xbytes * n_rhs;
+    // x-slice and halo, then (8-byte aligned) one residual accumulator per row
+    const int64_t xs = ((int64_t)p.max_part_rows + p.max_halo) * p.xbytes * n_rhs;
+    const int64_t ab = acc_bytes(p.value_dtype);
+    const int64_t acc = p.ner_slices > 0 ? (int64_t)p.max_part_rows * ab * n_rhs : 0;
+    return (acc > 0 ? (xs + ab - 1) / ab * ab : xs) + acc;
 }
 
 // Residual position of every permuted row (e*C + r, or -1), from er_row.
@@ -616,7 +621,7 @@ ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, c
         if (prm.n_rhs == 0) prm.n_rhs = 1;
         if (prm.n_rhs != 1 && prm.n_rhs != 2 && prm.n_rhs != 4 && prm.n_rhs != 8)
             return fail(EHYB_EINVAL, "n_rhs must be 1, 2, 4 or 8");
-        if (prm.value_dtype < 0 || prm.value_dtype > 2) return fail(EHYB_EINVAL, "unknown value dtype");
+        if (!valid_dtype(prm.value_dtype)) return fail(EHYB_EINVAL, "unknown value dtype");
         if (prm.rows_per_wave == 0) prm.rows_per_wave = kWave;
         if (prm.rows_per_wave < 1 || prm.rows_per_wave > kWave ||
             (prm.rows_per_wave & (prm.rows_per_wave - 1)))
@@ -638,15 +643,18 @@ ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, c
         P->n = n;
         P->nnz = A->nnz;
         P->value_dtype = prm.value_dtype;
-        P->vbytes = prm.value_dtype == EHYB_F64 ? 8 : (prm.value_dtype == EHYB_F32 ? 4 : 2);
-        P->xbytes = prm.value_dtype == EHYB_F64 ? 8 : 4;
+        P->vbytes = value_bytes(prm.value_dtype);
+        P->xbytes = x_bytes(prm.value_dtype);
         P->C = prm.rows_per_wave;
         P->L = kWave / prm.rows_per_wave;
         P->kc = kc_for(prm.value_dtype);
         // LDS per partition row: its x elements and its residual accumulators
         P->n_rhs = prm.n_rhs;
-        const int64_t tau = 2 * (int64_t)P->xbytes * prm.n_rhs;
-        const int64_t max_rows = std::min<int64_t>(65535, (prm.lds_bytes - kStaticLds) / tau);
+        // LDS per partition row: its x element and its residual accumulator
+        const int64_t tau = ((int64_t)P->xbytes + acc_bytes(prm.value_dtype)) * prm.n_rhs;
+        // (8-byte accumulators after 4-byte x elements may need 4 bytes of alignment)
+        const int64_t align_pad = acc_bytes(prm.value_dtype) > P->xbytes ? acc_bytes(prm.value_dtype) - P->xbytes : 0;
+        const int64_t max_rows = std::min<int64_t>(65535, (prm.lds_bytes - kStaticLds - align_pad) / tau);
         if (max_rows < 1) return fail(EHYB_EINVAL, "lds_bytes smaller than one partition row");
         // Eq. 1-2: smallest K with n*tau/(K*P) < SHM, VecSize = ceil(n/(K*P))
         int64_t K = 1;
@@ -658,7 +666,7 @@ ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, c
                 1, std::min<int64_t>(max_rows, std::max<int64_t>(vec, std::min<int64_t>(n, 512))));
         if (prm.slice_rows < 1) return fail(EHYB_EINVAL, "slice_rows must be >= 1");
         if (prm.slice_rows > max_rows)
-            return fail(EHYB_EINVAL, "slice_rows exceeds the LDS budget (2 * x bytes per row) or 65535 rows");
+            return fail(EHYB_EINVAL, "slice_rows exceeds the LDS budget (x element + accumulator per row) or 65535 rows");
         const int64_t cap = std::min<int64_t>(max_rows, prm.slice_rows + (int64_t)prm.slice_rows * prm.imbalance_pct / 100);
         const int32_t nparts_req = n > 0 ? (int32_t)((n + prm.slice_rows - 1) / prm.slice_rows) : 0;
         // ELL width cap: -1 none (the paper's split), > 0 as given, 0 the
@@ -719,7 +727,11 @@ ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, c
                 for (int64_t i = 0; i < n; ++i) sizes[part[i]]++;
                 for (int32_t s2 : sizes) maxp = std::max(maxp, s2);
             }
-            const int64_t room = (int64_t)(prm.lds_bytes - kStaticLds) / ((int64_t)P->xbytes * prm.n_rhs) - 2 * (int64_t)maxp;
+            const int64_t room =
+                acc_bytes(prm.value_dtype) == P->xbytes
+                    ? (int64_t)(prm.lds_bytes - kStaticLds) / ((int64_t)P->xbytes * prm.n_rhs) - 2 * (int64_t)maxp
+                    : ((int64_t)(prm.lds_bytes - kStaticLds - align_pad) / prm.n_rhs -
+                       (int64_t)maxp * (P->xbytes + acc_bytes(prm.value_dtype))) / P->xbytes;
             halo_cap = (int32_t)std::max<int64_t>(0, std::min<int64_t>(room, 65535 - (int64_t)maxp));
             if (prm.halo_rows > 0) halo_cap = std::min(halo_cap, prm.halo_rows);
         }
@@ -964,7 +976,9 @@ const char* validate_loaded(const ehyb_plan& P) {
     }
     if (maxh != P.max_halo) return "plan file largest halo is inconsistent";
     if (lds_bytes_used(P, P.n_rhs) > 160 * 1024 - kStaticLds) return "plan file needs more LDS than a workgroup has";
-    const int64_t max_rows = std::min<int64_t>(65535, (int64_t)(160 * 1024 - kStaticLds) / (2 * P.xbytes * P.n_rhs));
+    const int64_t max_rows = std::min<int64_t>(
+        65535, (int64_t)(160 * 1024 - kStaticLds - (acc_bytes(P.value_dtype) > P.xbytes ? 4 : 0)) /
+                   (((int64_t)P.xbytes + acc_bytes(P.value_dtype)) * P.n_rhs));
     for (int32_t p = 0; p < P.nparts; ++p) {
         const int64_t sz = (int64_t)P.part_start[p + 1] - P.part_start[p];
         const int64_t sl = (int64_t)P.slice_start[p + 1] - P.slice_start[p];
@@ -1109,11 +1123,11 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         r.pod(P->nnz_halo);
         r.pod(P->max_halo);
         if (!r.ok || P->n < 0 || P->n > INT32_MAX || P->nparts < 0 || P->nslices < 0 || P->ner_slices < 0 ||
-            P->value_dtype < 0 || P->value_dtype > 2 || P->L < 1 || P->L > kWave || P->C * P->L != kWave ||
+            !valid_dtype(P->value_dtype) || P->L < 1 || P->L > kWave || P->C * P->L != kWave ||
             P->kc != kc_for(P->value_dtype) || P->ell_slots < 0 || P->er_slots < 0 || P->max_part_rows < 0)
             return fail(EHYB_EINVAL, "plan file header is inconsistent");
-        P->vbytes = P->value_dtype == EHYB_F64 ? 8 : (P->value_dtype == EHYB_F32 ? 4 : 2);
-        P->xbytes = P->value_dtype == EHYB_F64 ? 8 : 4;
+        P->vbytes = value_bytes(P->value_dtype);
+        P->xbytes = x_bytes(P->value_dtype);
         P->n_rhs = P->params.n_rhs;
         if (P->n_rhs != 1 && P->n_rhs != 2 && P->n_rhs != 4 && P->n_rhs != 8)
             return fail(EHYB_EINVAL, "plan file right-hand side count is invalid");

@@ -15,7 +15,22 @@ namespace ehyb {
 
 constexpr int kWave = 64;              // gfx950 wavefront width
 // ELL entries per lane per load step: 16 bytes of values (FP64 2, FP32 4, BF16 8)
-constexpr int kc_for(int value_dtype) { return value_dtype == EHYB_F64 ? 2 : (value_dtype == EHYB_F32 ? 4 : 8); }
+// How a plan's values are stored (the ACC64 types store like F32 / BF16).
+constexpr int storage_dtype(int value_dtype) {
+    return value_dtype == EHYB_F32_ACC64 ? EHYB_F32 : (value_dtype == EHYB_BF16_ACC64 ? EHYB_BF16 : value_dtype);
+}
+constexpr int kc_for(int value_dtype) {
+    return storage_dtype(value_dtype) == EHYB_F64 ? 2 : (storage_dtype(value_dtype) == EHYB_F32 ? 4 : 8);
+}
+constexpr int value_bytes(int value_dtype) {
+    return storage_dtype(value_dtype) == EHYB_F64 ? 8 : (storage_dtype(value_dtype) == EHYB_F32 ? 4 : 2);
+}
+constexpr int x_bytes(int value_dtype) { return value_dtype == EHYB_F64 ? 8 : 4; }
+// bytes of one residual accumulator in LDS
+constexpr int acc_bytes(int value_dtype) {
+    return (value_dtype == EHYB_F64 || value_dtype == EHYB_F32_ACC64 || value_dtype == EHYB_BF16_ACC64) ? 8 : 4;
+}
+constexpr bool valid_dtype(int value_dtype) { return value_dtype >= EHYB_F64 && value_dtype <= EHYB_BF16_ACC64; }
 constexpr size_t kBlobAlign = 256;
 constexpr int kStaticLds = 64;         // LDS the SpMV kernel keeps for its queue counters
 // A residual row that would need more than kWideSteps load steps on its L

@@ -16,13 +16,29 @@ import pytest
 import matgen
 import oracle
 from oracle.precision import gamma32, quantize
-from paper_2204_06666_amd import EHYB_BF16, EHYB_F32, Plan
+from paper_2204_06666_amd import EHYB_BF16, EHYB_BF16_ACC64, EHYB_F32, EHYB_F32_ACC64, Plan
 
 pytestmark = pytest.mark.gpu
 
 import torch  # noqa: E402
 
-DT = {EHYB_F32: ("f32", 2.0 ** -24), EHYB_BF16: ("bf16", 2.0 ** -8)}
+DT = {EHYB_F32: ("f32", 2.0 ** -24), EHYB_BF16: ("bf16", 2.0 ** -8),
+      EHYB_F32_ACC64: ("f32", 2.0 ** -24), EHYB_BF16_ACC64: ("bf16", 2.0 ** -8)}
+ACC64 = (EHYB_F32_ACC64, EHYB_BF16_ACC64)
+
+
+def gamma64(m):
+    u = 2.0 ** -53
+    m = np.asarray(m, dtype=np.float64)
+    return m * u / (1.0 - m * u)
+
+
+def acc_bound(dt, m):
+    """Accumulation bound relative to sum |a_q x_q|: binary32 sums, or binary64
+    sums rounded to binary32 once."""
+    if dt in ACC64:
+        return 2.0 ** -24 + gamma64(m + 2) * (1 + 2.0 ** -24)
+    return gamma32(m + 2)
 
 
 def _run(A, x, dt, permuted=True, **kw):
@@ -47,13 +63,13 @@ def _check(A, x, y, dt, what):
     yq = oracle.spmv(Aq, xq)
     sq = oracle.abs_scale(Aq, xq)
     err_q = np.abs(y - yq)
-    bound_q = gamma32(m + 2) * sq
+    bound_q = acc_bound(dt, m) * sq
     bad = ~((err_q <= bound_q) | ((sq == 0) & (y == yq)))
     assert not bad.any(), f"{what}: row {np.argmax(bad)} err {err_q[bad].max():.3e} vs quantized reference"
     y64 = oracle.spmv(A, x)
     s64 = oracle.abs_scale(A, x)
     scaled = oracle.scaled_error(y, y64, s64)
-    bound = uv + 2.0 ** -24 + gamma32(m + 2) * (1 + uv) * (1 + 2.0 ** -24)
+    bound = uv + 2.0 ** -24 + acc_bound(dt, m) * (1 + uv) * (1 + 2.0 ** -24)
     assert np.all(scaled <= bound * (1 + 1e-6) + (s64 == 0) * 0), f"{what}: error vs FP64 above the bound"
     print(f"[precision] {what}: max scaled error vs FP64 {scaled.max():.3e} "
           f"(bound {np.max(bound):.3e}), vs quantized {np.max(err_q / np.where(sq > 0, sq, 1)):.3e}",
@@ -70,12 +86,14 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("dt", [EHYB_F32, EHYB_BF16])
+@pytest.mark.parametrize("dt", [EHYB_F32, EHYB_BF16, EHYB_F32_ACC64, EHYB_BF16_ACC64])
 @pytest.mark.parametrize("name,make,kw", CASES, ids=[c[0] for c in CASES])
 @pytest.mark.parametrize("rpw,halo", [(64, 0), (16, -1), (8, 0)])
 def test_low_precision_parity(dt, name, make, kw, rpw, halo):
     A = make()
     x = matgen.uniform_vector(A.n_rows, 321)
+    if dt in ACC64:       # 8-byte accumulators: 12 bytes of LDS per partition row
+        kw = dict(kw, slice_rows=min(kw["slice_rows"], (160 * 1024 - 68) // 12))
     y, _ = _run(A, x, dt, rows_per_wave=rpw, halo_rows=halo, **kw)
     _check(A, x, y, dt, f"{DT[dt][0]} {name} rpw={rpw} halo={halo}")
 
@@ -88,7 +106,7 @@ def test_low_precision_unpermuted(dt):
     _check(A, x, y, dt, f"{DT[dt][0]} unpermuted")
 
 
-@pytest.mark.parametrize("dt", [EHYB_F32, EHYB_BF16])
+@pytest.mark.parametrize("dt", [EHYB_F32, EHYB_BF16, EHYB_F32_ACC64, EHYB_BF16_ACC64])
 def test_integer_values_exact(dt):
     """Small integers are exact in bfloat16 and their sums in binary32."""
     A = matgen.random_small(400, 0.05, 11, integer=True, empty_rows=5)
@@ -97,7 +115,7 @@ def test_integer_values_exact(dt):
     assert np.array_equal(y, oracle.spmv(A, x))
 
 
-@pytest.mark.parametrize("dt", [EHYB_F32, EHYB_BF16])
+@pytest.mark.parametrize("dt", [EHYB_F32, EHYB_BF16, EHYB_BF16_ACC64])
 def test_low_precision_deterministic(dt):
     A = matgen.knn_fem(3000, perm_seed=4, pt_seed=5, val_seed=6)
     P = Plan(A, value_dtype=dt, slice_rows=2500).upload("cuda:0")
@@ -105,3 +123,27 @@ def test_low_precision_deterministic(dt):
     y0 = P.spmv(x).clone()
     for _ in range(10):
         assert torch.equal(P.spmv(x).view(torch.int32), y0.view(torch.int32))
+
+
+@pytest.mark.parametrize("rpw", [64, 8])
+def test_acc64_keeps_long_rows_accurate(rpw):
+    """Rows of ~1800 entries: with binary64 accumulation the result is the
+    binary32 rounding of the exact product of the stored values and x (error
+    at most 2^-24 of sum |a_q x_q|); binary32 accumulation is measurably worse."""
+    g = matgen.rng(77)
+    n = 2000
+    dense = g.uniform(-1, 1, (n, n)) * (g.random((n, n)) < 0.9)
+    A = matgen.from_dense(dense)
+    x = matgen.uniform_vector(n, 78)
+    errs = {}
+    for dt in (EHYB_F32, EHYB_F32_ACC64):
+        y, _ = _run(A, x, dt, rows_per_wave=rpw, slice_rows=700, halo_rows=-1)
+        Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, "f32"))
+        xq = x.astype(np.float32).astype(np.float64)
+        yq = oracle.spmv(Aq, xq)
+        sq = oracle.abs_scale(Aq, xq)
+        errs[dt] = float(np.max(np.abs(y - yq) / sq))
+    print(f"[precision] long rows rpw={rpw}: binary32 accumulation {errs[EHYB_F32]:.2e}, "
+          f"binary64 {errs[EHYB_F32_ACC64]:.2e}", flush=True)
+    assert errs[EHYB_F32_ACC64] <= 2.0 ** -24 * 1.001
+    assert errs[EHYB_F32] > 4 * errs[EHYB_F32_ACC64]

@@ -13,11 +13,11 @@ from oracle.structure import check_plan, layout_spmv
 from paper_2204_06666_amd import EhybError, Plan, _abi
 
 
-def _full_check(A, plan, value_dtype=np.float64, width_cap=None, x_seed=7, x_bytes=8):
+def _full_check(A, plan, value_dtype=np.float64, width_cap=None, x_seed=7, x_bytes=8, acc_bytes=None):
     if width_cap is None:
         width_cap = plan.stats()["ell_width_cap"]      # the cap in effect (automatic by default)
     v = plan.arrays()
-    st = check_plan(A, v, width_cap=width_cap, value_dtype=value_dtype, x_bytes=x_bytes)
+    st = check_plan(A, v, width_cap=width_cap, value_dtype=value_dtype, x_bytes=x_bytes, acc_bytes=acc_bytes)
     perm = v["perm"]
     # decode == P A P^T, values bit for bit
     rp, ci, val = plan.decode()
@@ -153,22 +153,23 @@ def test_tiny_and_empty():
     assert P.stats()["nnz"] == 0
 
 
-@pytest.mark.parametrize("dt,vt,kc", [(1, np.float32, 4), (2, "bf16", 8)])
+@pytest.mark.parametrize("dt,vt,kc", [(1, np.float32, 4), (2, "bf16", 8), (3, np.float32, 4), (4, "bf16", 8)])
 @pytest.mark.parametrize("halo", [0, -1])
 def test_low_precision_plan_values_rounded(dt, vt, kc, halo):
-    """FP32 and BF16 plans store each value rounded to nearest even directly
-    from FP64 (checked bit for bit by the oracle's own rounding), with 16
-    bytes of values per lane per step."""
+    """FP32 and BF16 plans (and their binary64-accumulation variants, whose
+    residual accumulators take 8 bytes of LDS) store each value rounded to
+    nearest even directly from FP64 (checked bit for bit by the oracle's own
+    rounding), with 16 bytes of values per lane per step."""
     A = matgen.stencil3d(10, perm_seed=1, val_seed=2)
     P = Plan(A, slice_rows=300, value_dtype=dt, halo_rows=halo)
     assert P.stats()["kc"] == kc
-    _full_check(A, P, value_dtype=vt, x_bytes=4)
+    _full_check(A, P, value_dtype=vt, x_bytes=4, acc_bytes=8 if dt >= 3 else 4)
     v = P.arrays()
     from oracle.precision import quantize
     from oracle.structure import layout_spmv
     x = matgen.uniform_vector(A.n_rows, 3)
     perm = v["perm"]
-    Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, "f32" if dt == 1 else "bf16"))
+    Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, "f32" if dt in (1, 3) else "bf16"))
     yq = oracle.spmv(Aq, x)[perm]
     oracle.assert_close(layout_spmv(v, x[perm]), yq, oracle.abs_scale(Aq, x)[perm], what="quantized layout")
 
@@ -198,7 +199,7 @@ def test_row_ptr_inconsistent():
 
 
 @pytest.mark.parametrize("kw", [{"slice_rows": 10241}, {"rows_per_wave": 3}, {"rows_per_wave": 128},
-                                {"value_dtype": 7}, {"lds_bytes": 200000}, {"imbalance_pct": -1},
+                                {"value_dtype": 7}, {"value_dtype": 5}, {"lds_bytes": 200000}, {"imbalance_pct": -1},
                                 {"partitioner": 5}, {"ell_width_cap": -2}])
 def test_invalid_params_rejected(kw):
     A = matgen.poisson2d(8)
@@ -334,3 +335,20 @@ def test_automatic_width_cap_sends_hub_rows_to_wide_slices():
     a1, a2 = Plan(B, slice_rows=800).arrays(), Plan(B, slice_rows=800, ell_width_cap=-1).arrays()
     for k in ("perm", "ell_val", "ell_col", "er_col"):
         assert np.array_equal(a1[k], a2[k]), k
+
+
+
+def test_acc64_plans_size_lds_for_8_byte_accumulators():
+    """Binary64 accumulation: LDS per row = 4-byte x element + 8-byte
+    accumulator (aligned), so the largest partition is smaller than for FP32."""
+    A = matgen.stencil3d(30, perm_seed=1, val_seed=2)
+    lim32 = (160 * 1024 - 64) // 8
+    lim64 = (160 * 1024 - 64 - 4) // 12
+    Plan(A, value_dtype=3, slice_rows=lim64, halo_rows=-1)
+    with pytest.raises(EhybError):
+        Plan(A, value_dtype=3, slice_rows=lim64 + 1)
+    Plan(A, value_dtype=1, slice_rows=lim32)
+    P = Plan(A, value_dtype=4, slice_rows=lim64, halo_rows=-1, imbalance_pct=0)
+    st = P.stats()
+    assert st["lds_bytes_used"] <= 160 * 1024 - 64
+    _full_check(A, P, value_dtype="bf16", x_bytes=4, acc_bytes=8)
