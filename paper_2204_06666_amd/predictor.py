@@ -24,7 +24,7 @@ SHAPES = [("W1", (N_HID, N_IN)), ("b1", (N_HID,)), ("W2", (N_HID, N_HID)), ("b2"
 # down to 256 rows so that matrices of 10^4 - 10^5 rows can still spread over
 # the 256 CUs; 0 is the LDS limit ((160 KiB - 64) / 8 rows).
 SLICE_ROWS = (256, 512, 1024, 2048, 4096, 0)
-WIDTH_QUANTILES = (None, 0.99, 0.90, 0.75)        # ELL width cap: none or a row-length quantile
+WIDTH_QUANTILES = (None, 0.99, 0.90, 0.75)        # ELL width cap: the library's automatic cap or a row-length quantile
 ROWS_PER_WAVE = (8, 16, 32, 64)
 
 
@@ -146,7 +146,8 @@ def decode_output(y: np.ndarray):
 
 
 def width_cap(row_lengths: np.ndarray, q) -> int:
-    """ELL width cap of quantile q (lower quantile of the row lengths, at least 1); 0 = none."""
+    """ELL width cap of quantile q (lower quantile of the row lengths, at least 1);
+    None gives 0, the library's automatic cap."""
     if q is None:
         return 0
     s = np.sort(np.asarray(row_lengths))
