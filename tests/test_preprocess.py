@@ -94,6 +94,44 @@ def test_partitioner_beats_scrambled_blocks():
     assert ml["nnz_er"] / ml["nnz"] < 0.08
 
 
+def _grid_partition(shape, block, perm_seed):
+    """Partition of a relabelled grid (matgen's labelling) into axis-aligned
+    boxes of `block` nodes per side: part[label[node]] = box of node."""
+    n = int(np.prod(shape))
+    lab = matgen._relabel(n, perm_seed)
+    coords = np.unravel_index(np.arange(n), shape)
+    nb = [s // b for s, b in zip(shape, block)]
+    box = np.ravel_multi_index(tuple(c // b for c, b in zip(coords, block)), nb)
+    part = np.empty(n, dtype=np.int32)
+    part[lab] = box
+    return part
+
+
+def test_partitioner_cut_close_to_geometric_boxes():
+    """Closed forms of the cut of box partitions of a grid, and the
+    multilevel partitioner measured against them.  With the halo off, the
+    residual part holds exactly the entries whose column lies in another
+    partition (Section 3.1).  A 5-point 64x64 grid in 2x4 boxes of 32x16 cuts
+    64 + 3*64 edges, each stored twice: 512 entries.  In a 27-point m^3 grid,
+    a line of length m has 3m - 2 ordered neighbour pairs (offsets -1, 0, +1),
+    so the grid holds (3m - 2)^3 entries and a box of side b keeps (3b - 2)^3:
+    32^3 in 8^3 boxes cuts 94^3 - 64 * 22^3 = 149112.  The partitioner, blind to
+    the geometry, must stay within 1.3x (2-D) and 1.1x (3-D) of these cuts."""
+    A = matgen.config_matrix(1)
+    geo = Plan(A, slice_rows=512, halo_rows=-1, partition=_grid_partition((64, 64), (32, 16), 1000))
+    assert geo.stats()["nparts"] == 8 and geo.stats()["nnz_er"] == 512
+    _full_check(A, geo)
+    ml = Plan(A, slice_rows=512, halo_rows=-1).stats()
+    assert ml["nnz_er"] <= 1.3 * 512, ml["nnz_er"]
+
+    A = matgen.stencil3d(32, perm_seed=7, val_seed=8)
+    assert A.nnz == 94 ** 3
+    geo = Plan(A, slice_rows=512, halo_rows=-1, partition=_grid_partition((32, 32, 32), (8, 8, 8), 7))
+    assert geo.stats()["nparts"] == 64 and geo.stats()["nnz_er"] == 94 ** 3 - 64 * 22 ** 3
+    ml = Plan(A, slice_rows=512, halo_rows=-1).stats()
+    assert ml["nnz_er"] <= 1.1 * (94 ** 3 - 64 * 22 ** 3), ml["nnz_er"]
+
+
 def test_eq1_default_slice_rows():
     A = matgen.stencil3d(100, points=7)   # n = 1e6
     n = A.n_rows
