@@ -77,6 +77,24 @@ def time_cold(torch, fn, flush, reps):
     return statistics.median(ts)
 
 
+def fp64_products(row_ptr, col, val, X):
+    """A X and |A| |X| in FP64 by scipy's CSR product: the reference of the
+    errors this benchmark reports (the row-by-row checks against the oracle
+    are the tests' job)."""
+    import numpy as np
+    import scipy.sparse as sp
+    n = len(row_ptr) - 1
+    S = sp.csr_matrix((val, col, row_ptr), shape=(n, n))
+    return S @ X, abs(S) @ np.abs(X)
+
+
+def scaled_error(y, ref, scale):
+    """|y - ref| / scale per entry; 0 where both are exact zeros of a zero scale."""
+    import numpy as np
+    err = np.abs(y - ref)
+    return np.where(scale > 0, err / np.where(scale > 0, scale, 1.0), np.where(err == 0, 0.0, np.inf))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,13 +304,11 @@ def main():
 def run_precision(args):
     """Unstructured-FEM matrix (mutual kNN, 3x3 blocks): FP64 values against
     FP32 and BF16 values with binary32 x and accumulation, each with its error
-    against the FP64 oracle."""
+    against the FP64 product of the original values (scipy's CSR product)."""
     import numpy as np
     import torch
 
     import matgen
-    import oracle
-    from oracle.precision import quantize
     from paper_2204_06666_amd import EHYB_BF16, EHYB_BF16_ACC64, EHYB_F32, EHYB_F32_ACC64, EHYB_F64, Plan
 
     dev = torch.device("cuda:0")
@@ -301,9 +317,8 @@ def run_precision(args):
     x = matgen.uniform_vector(A.n_rows, matgen.CONFIG_SEEDS[3] + 2)
     n, nnz = A.n_rows, A.nnz
     flops = 2.0 * nnz
-    log(f"n={n} nnz={nnz}; FP64 oracle")
-    y64 = oracle.spmv(A, x)
-    s64 = oracle.abs_scale(A, x)
+    log(f"n={n} nnz={nnz}; FP64 reference product")
+    y64, s64 = fp64_products(A.row_ptr, A.col, A.val, x)
     res = {}
     for name, dt in (("f64", EHYB_F64), ("f32", EHYB_F32), ("bf16", EHYB_BF16), ("f32_acc64", EHYB_F32_ACC64),
                      ("bf16_acc64", EHYB_BF16_ACC64)):
@@ -319,7 +334,7 @@ def run_precision(args):
         yp = yt.cpu().numpy().astype(np.float64)
         y = np.empty_like(yp)
         y[perm] = yp
-        e = oracle.scaled_error(y, y64, s64)
+        e = scaled_error(y, y64, s64)
         res[name] = {"GFLOPs": round(flops / wall / 1e9, 2), "us_per_step": round(wall * 1e6, 2),
                      "algorithmic_bytes": st["algorithmic_bytes"],
                      "algorithmic_GBps": round(st["algorithmic_bytes"] / kern / 1e9, 1),
@@ -329,10 +344,12 @@ def run_precision(args):
                      "nparts": st["nparts"], "nnz_er": st["nnz_er"], "nnz_halo": st["nnz_halo"],
                      "preprocess_s": round(t_pre, 2)}
         if dt != EHYB_F64:
-            Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, name.split("_")[0]))
-            xq = x.astype(np.float32).astype(np.float64)
-            eq = oracle.scaled_error(y, oracle.spmv(Aq, xq), oracle.abs_scale(Aq, xq))
-            res[name]["max_row_scaled_error_vs_quantized"] = float(eq.max())
+            # against the FP64 product of the values as the plan stores them
+            # (P A P^T decoded) and x as the kernel reads it, in plan order
+            rp, ci, v = plan.decode()
+            yq, sq = fp64_products(rp, ci, v, xt.cpu().numpy().astype(np.float64))
+            res[name]["max_row_scaled_error_vs_quantized"] = float(scaled_error(yp, yq, sq).max())
+            del rp, ci, v
         log(f"{name}: {res[name]}")
         del plan, xt, yt
     out = {
@@ -357,8 +374,6 @@ def run_batched(args):
     import torch
 
     import matgen
-    import oracle
-    from oracle.precision import gamma32, quantize
     from paper_2204_06666_amd import EHYB_F32, Batch, Plan
 
     nrhs = 8
@@ -410,24 +425,22 @@ def run_batched(args):
     wall_g, kern_g = time_launches(torch, graph.replay, args.steps, args.warmup)
     torch.cuda.synchronize()
 
-    # accuracy: every matrix against the FP64 product of the stored (binary32)
-    # values and binary32 x, within the binary32 accumulation bound
-    log("checking all matrices against the oracle")
+    # accuracy: every matrix against the FP64 product of its stored (binary32)
+    # values and binary32 X, in plan order; the binary32 accumulation bound
+    # gamma_{m+2}(2^-24) * (|A| |X|) per entry must hold
+    log("checking all matrices against the FP64 product of the stored values")
     worst = 0.0
-    for i, ((_, A), p, x, y) in enumerate(zip(mats, plans, X, Yd)):
+    u32 = 2.0 ** -24
+    for i, (p, y, xd) in enumerate(zip(plans, Yd, Xd)):
         if i % 16 == 15:
             log(f"  {i + 1} matrices checked")
-        Aq = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, quantize(A.val, "f32"))
-        xq = x.astype(np.float32).astype(np.float64)
-        ref = oracle.spmm(Aq, xq)
-        sc = oracle.spmm(matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, np.abs(Aq.val)), np.abs(xq))
-        got = np.empty_like(ref)
-        got[p.perm()] = y.cpu().numpy()
-        bound = gamma32(np.diff(A.row_ptr) + 2)[:, None] * sc
-        err = np.abs(got - ref)
-        if not np.all((err <= bound) | ((sc == 0) & (got == ref))):
+        rp, ci, v = p.decode()
+        ref, sc = fp64_products(rp, ci, v, xd.cpu().numpy().astype(np.float64))
+        m = np.diff(rp).astype(np.float64)[:, None] + 2.0
+        e = scaled_error(y.cpu().numpy().astype(np.float64), ref, sc)
+        if not np.all(e <= m * u32 / (1.0 - m * u32)):
             raise SystemExit("batched result outside the binary32 accumulation bound")
-        worst = max(worst, float(np.max(err / np.where(sc > 0, sc, 1.0))))
+        worst = max(worst, float(e.max()))
 
     log("separate products: plans for one right-hand side, 8 launches per matrix")
     single = []
@@ -462,6 +475,7 @@ def run_batched(args):
 
     cpu = None
     if not args.no_cpu:
+        import oracle
         log("CPU oracle on the first matrices (bounded sample)")
         t0 = time.perf_counter()
         done_nnz, used = 0, []
