@@ -102,7 +102,8 @@ typedef struct {
                                At most lds_bytes/tau and 65536 rows. */
     int32_t ell_width_cap;  /* max ELL entries per row: > 0 as given; -1 =
                                unlimited (the paper's split by partition
-                               only); 0 = automatic, 128 load steps per lane
+                               only; a row-slice wider than 65535 entries per
+                               lane is EHYB_EUNSUPPORTED); 0 = automatic, 128 load steps per lane
                                group (128 * lanes per row * kc entries), which
                                only hub rows reach: their excess entries go
                                to the residual part, where they run on wide
@@ -158,7 +159,7 @@ typedef struct {
     int32_t max_part_rows;    /* largest partition */
     int32_t rows_per_slice;   /* C = rows_per_wave */
     int32_t lanes_per_row;    /* L = 64 / C */
-    int32_t kc;               /* ELL entries per lane per load step */
+    int32_t kc;               /* ELL entries per lane per full load step */
     int32_t value_dtype;      /* ehyb_dtype */
     int32_t eq1_K;            /* K of Eq. 1 for this n (informational) */
     int32_t max_halo;         /* largest halo of one partition */
@@ -180,10 +181,13 @@ typedef struct {
  * slices [slice_start[p], slice_start[p+1]).  They are stored in the order a
  * workgroup takes them: first the ell_free[p] slices none of whose rows has
  * residual entries, then the others, each group by ascending row.
- * ell_meta[4s..4s+3] = slot offset; step count (low 16 bits) and the slice's
- * index j within its partition (high 16 bits: row r of the slice is local row
- * j*C + r); a 64-bit mask (low word, high word) whose bit r says that row r
- * also has residual entries.  Columns are 16-bit indices into the
+ * ell_meta[4s..4s+3] = slot offset; width W, the entries each lane loads
+ * (low 16 bits), and the slice's index j within its partition (high 16 bits:
+ * row r of the slice is local row j*C + r); a 64-bit mask (low word, high
+ * word) whose bit r says that row r also has residual entries.  A slice of
+ * width W holds 64*W slots: W / KC steps of KC entries per lane, then
+ * W % KC single-entry steps, so a row of m ELL entries needs W = (m / (L*KC))*KC
+ * + ceil((m mod L*KC) / L), with no padding beyond the longest row.  Columns are 16-bit indices into the
  * partition's LDS vector: c < size of the partition is x-slice element c
  * (permuted row part_start[p] + c); c >= size is halo element
  * halo_idx[halo_start[p] + c - size].
@@ -205,12 +209,14 @@ typedef struct {
  * Columns are permuted global indices.
  *
  * Slots: entry k (ascending permuted column) of row r of a slice with slot
- * offset `off` lives at
+ * offset `off` and F full steps lives, for k < F*L*KC, at
  *   t = k / (L*KC), u = (k / KC) % L, c = k % KC, lane = r*L + u,
  *   slot = off + (t*64 + lane)*KC + c,
- * with KC = kc in the ELL part and KC = 1 in the residual part; in a wide
- * residual slice, L = 64 and r = 0 (entry k at off + k).  Each step of a
- * slice holds 64*KC slots.  Padding slots hold +0.0 and column 0. */
+ * and otherwise, with k' = k - F*L*KC, in single-entry step t' = k' / L at
+ *   slot = off + F*64*KC + t'*64 + r*L + k' % L.
+ * In the ELL part KC = kc and F = W / kc; in the residual part KC = 1 and F
+ * is the step count; in a wide residual slice, L = 64 and r = 0 (entry k at
+ * off + k).  Padding slots hold +0.0 and column 0. */
 typedef struct {
     int64_t n;
     int32_t nparts, nslices, ner_slices, lanes_per_row, kc, value_dtype;

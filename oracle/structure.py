@@ -20,19 +20,26 @@ properties the paper fixes for the format:
   of Alg. 2 moves values without touching them).
 
 Layout rules being checked (row-slice = C = 64 / L rows, one 64-lane
-wavefront per row-slice, L lanes per row, KC consecutive entries per lane per
-step).  ELL part: partition p's rows, in order, cut into row-slices; row r of
+wavefront per row-slice, L lanes per row).  ELL part: partition p's rows, in order, cut into row-slices; row r of
 an ELL slice with index j is local row j*C + r.  Residual part: the rows
 of partition p that have residual entries, by non-increasing residual count
 (ties by local row), cut into row-slices; row r of residual slice e is local
 row er_row[e, r] (0xFFFF: none).  When C > 1, every residual row with more
 than 32*L residual entries comes first, in a "wide" slice of its own (bit 31
-of its step count, row at r = 0) laid out as if L were 64.  In either part
+of its step count, row at r = 0) laid out as if L were 64.
 
-    entry k (ascending column) of row r of a slice with slot offset `off` lives at
-        t = k // (L*KC), u = (k // KC) % L, c = k % KC, lane = r*L + u,
-        slot = off + (t*64 + lane)*KC + c,
-    with KC = kc in the ELL part and KC = 1 in the residual part.
+An ELL slice of width W (entries per lane) has F = W // kc full steps of kc
+consecutive entries per lane, then W % kc single-entry steps; a residual
+slice of S steps has F = S steps of one entry per lane.  Entry k (ascending
+column) of row r of a slice with slot offset `off` lives at
+
+    k <  F*L*KC:  t = k // (L*KC), u = (k // KC) % L, c = k % KC,
+                  slot = off + (t*64 + r*L + u)*KC + c,
+    k >= F*L*KC:  k1 = k - F*L*KC, slot = off + F*64*KC + (k1 // L)*64 + r*L + k1 % L,
+
+with KC = kc in the ELL part and KC = 1 in the residual part.  A slice holds
+64*W (ELL) or 64*S (residual) slots, and W is the least width that holds the
+slice's longest row: W = (m // (L*kc))*kc + ceil((m mod L*kc) / L).
 
 ELL columns are 16-bit indices into the partition's LDS vector: below the
 partition size an x-slice element, otherwise halo element
@@ -40,7 +47,7 @@ halo_idx[halo_start[p] + c - size].
 
 ``view`` is a mapping with the keys: n, nparts, L, kc, perm, part_start,
 halo_start, halo_idx, slice_start, er_slice_start, ell_free, ell_meta (uint32 [nslices, 4]: offset,
-steps | slice index << 16, residual-row mask low/high; slices without residual
+width | slice index << 16, residual-row mask low/high; slices without residual
 rows first), er_meta (uint32 [ner_slices, 2]: offset, steps | wide << 31),
 er_row (uint16 [ner_slices, C]), ell_val, ell_col (uint16), er_val, er_col
 (int32), row_ell_len, row_er_len.
@@ -64,8 +71,10 @@ WIDE_STEPS = 32      # a residual row longer than WIDE_STEPS * L entries is wide
 
 
 def _slice_rows(view, which: str):
-    """Per slice: (slot offset, steps, partition, rows[C], wide) with rows the
-    permuted row of each slice row or -1, and wide the wide-slice flag."""
+    """Per slice: (slot offset, lane width, partition, rows[C], wide): the lane
+    width is the ELL width W or the residual step count S (the slots of one
+    lane), rows the permuted row of each slice row or -1, wide the wide-slice
+    flag."""
     L = int(view["L"])
     C = 64 // L
     part_start = np.asarray(view["part_start"], dtype=np.int64)
@@ -82,18 +91,18 @@ def _slice_rows(view, which: str):
     _req((np.diff(starts) >= 0).all(), f"{which} slice bounds decrease")
     part = np.repeat(np.arange(nparts), np.diff(starts))
     if which == "ell":
-        steps = meta[:, 1] & 0xFFFF
+        width = meta[:, 1] & 0xFFFF
         j = meta[:, 1] >> 16
         local = j[:, None] * C + np.arange(C)[None, :]
         size = (part_start[part + 1] - part_start[part])[:, None]
         rows = np.where(local < size, part_start[part][:, None] + local, -1)
         wide = np.zeros(ns, dtype=bool)
     else:
-        steps = meta[:, 1] & (WIDE - 1)
+        width = meta[:, 1] & (WIDE - 1)
         wide = (meta[:, 1] & WIDE) != 0
         er_row = np.asarray(view["er_row"], dtype=np.int64).reshape(ns, C)
         rows = np.where(er_row != 0xFFFF, part_start[part][:, None] + er_row, -1)
-    return meta[:, 0], steps, part, rows, wide
+    return meta[:, 0], width, part, rows, wide
 
 
 def _slots(view, which: str):
@@ -104,21 +113,22 @@ def _slots(view, which: str):
     the row, whether it holds a real entry, and the slice's partition."""
     L = int(view["L"])
     kc = int(view["kc"]) if which == "ell" else 1
-    off, steps, part_of_slice, rows, wide = _slice_rows(view, which)
+    off, width, part_of_slice, rows, wide = _slice_rows(view, which)
     rowlen = np.asarray(view["row_ell_len"] if which == "ell" else view["row_er_len"],
                         dtype=np.int64)
     nslices = off.shape[0]
-    per = steps * 64 * kc
+    per = width * 64
     total = int(per.sum())
     s_of = np.repeat(np.arange(nslices), per)
     o = np.arange(total) - np.repeat(np.cumsum(per) - per, per)
-    t = o // (64 * kc)
-    lane = (o // kc) % 64
-    c = o % kc
+    full = (width // kc)[s_of]           # steps of kc entries per lane
     Ls = np.where(wide[s_of], 64, L)     # lanes per row of each slot's slice
+    in_full = o < full * 64 * kc
+    o1 = o - full * 64 * kc              # position among the single-entry steps
+    lane = np.where(in_full, (o // kc) % 64, o1 % 64)
     r = lane // Ls
     u = lane % Ls
-    k = (t * Ls + u) * kc + c
+    k = np.where(in_full, ((o // (64 * kc)) * Ls + u) * kc + o % kc, full * Ls * kc + (o1 // 64) * Ls + u)
     row = rows[s_of, r] if total else np.zeros(0, dtype=np.int64)
     exists = row >= 0
     valid = exists.copy()
@@ -279,19 +289,23 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
         tie = np.diff(cnt) == 0
         _req((np.diff(real)[tie] > 0).all(), "residual rows: unstable tie order")
 
-    for which, arr, width in (("ell", ell_val, 64 * kc), ("er", er_val, 64)):
-        off, steps, part_of_slice, rows, wide = _slice_rows(view, which)
-        end = off + steps * width
+    for which, arr in (("ell", ell_val), ("er", er_val)):
+        off, width, part_of_slice, rows, wide = _slice_rows(view, which)
+        end = off + width * 64
         _req((end <= arr.size).all(), "slot range past the end of its array")
         o = np.argsort(off, kind="stable")
-        nz = steps[o] > 0
+        nz = width[o] > 0
         _req((off[o][nz][1:] >= end[o][nz][:-1]).all(), "overlapping slot ranges")
-        # minimal widths: each slice's step count is what its longest row needs
+        # minimal widths: each slice is as wide as its longest row needs
         lens = row_ell_len if which == "ell" else row_er_len
-        per = L * kc if which == "ell" else np.where(wide, 64, L)
         rl = np.where(rows >= 0, lens[np.maximum(rows, 0)], 0)
         need = rl.max(axis=1) if rl.size else np.zeros(0, dtype=np.int64)
-        _req(np.array_equal(steps, -(-need // per)), f"{which} slice width is not its longest row")
+        if which == "ell":
+            fs = need // (L * kc)
+            want_w = fs * kc + -(-(need - fs * L * kc) // L)
+        else:
+            want_w = -(-need // np.where(wide, 64, L))
+        _req(np.array_equal(width, want_w), f"{which} slice width is not its longest row")
         if which == "ell":
             meta = np.asarray(view["ell_meta"], dtype=np.uint64).reshape(-1, 4)
             mask = meta[:, 2] | (meta[:, 3] << np.uint64(32))
@@ -371,7 +385,7 @@ def check_plan(A, view, x_bytes: int = 8, lds_budget: int = 160 * 1024, width_ca
     return {
         "nnz": int(B.nnz), "nnz_ell": int(in_ell.sum()), "nnz_er": nnz_er,
         "nnz_halo": int((in_ell & ~same).sum()), "n_halo": int(halo_idx.size),
-        "ell_slots": int((np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)[:, 1] & 0xFFFF).sum() * 64 * kc),
+        "ell_slots": int((np.asarray(view["ell_meta"], dtype=np.int64).reshape(-1, 4)[:, 1] & 0xFFFF).sum() * 64),
         "er_slots": int((np.asarray(view["er_meta"], dtype=np.int64).reshape(-1, 2)[:, 1] & (WIDE - 1)).sum() * 64),
         "n_er_wide": int(er_wide.sum()),
         "er_fraction": nnz_er / max(1, B.nnz), "nparts": nparts,

@@ -255,8 +255,10 @@ struct Queues {
 //     slice's metadata is fetched while the current one is processed;
 //  3. ELL queue (slices without residual rows first): a wavefront takes a
 //     row-slice, issues all its loads (up to kEll steps of 16 bytes of values
-//     and KC columns per lane) before using any, multiply-adds against the
-//     LDS vector (x-slice and halo) and stores y once.  A slice with residual
+//     and KC columns per lane) before using any, then the slice's last
+//     entries (fewer than KC per lane, one value and column per step),
+//     multiply-adds against the LDS vector (x-slice and halo) and stores y
+//     once.  A slice with residual
 //     rows first waits until the residual queue is drained, then adds the
 //     residual sums.
 // Wavefronts that leave the residual queue early stream ELL slices while
@@ -436,7 +438,9 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
         // the next slice's metadata travels while this slice streams
         const uint4 mn = nxt < ns ? a.ell_meta[s0 + nxt] : make_uint4(0, 0, 0, 0);
         const uint4 mu = uniform4(m);
-        const uint32_t steps = mu.y & 0xFFFFu;
+        const uint32_t width = mu.y & 0xFFFFu;  // entries per lane
+        const uint32_t steps = width / KC;      // steps of KC entries, then
+        const uint32_t tail = width % KC;       // single-entry steps
         const int j0 = (int)(mu.y >> 16);
         const VL* v2 = reinterpret_cast<const VL*>(ell_val + mu.x) + lane;
         const CL* c2 = reinterpret_cast<const CL*>(a.ell_col + mu.x) + lane;
@@ -465,6 +469,27 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
                         for (int k = 0; k < NRHS; ++k)
                             acc[k] = fma(val[e], (Acc)lane_of<X, NRHS>(xv, k), acc[k]);
                     }
+                }
+        }
+        if (tail != 0) {
+            // the slice's last entries: one value and one column per lane per
+            // step, so that rows are not padded to a multiple of KC
+            const size_t tb = (size_t)mu.x + (size_t)steps * kWave * KC + lane;
+            V tv[KC - 1];
+            uint16_t tc[KC - 1];
+#pragma unroll
+            for (int j = 0; j < KC - 1; ++j)
+                if (j < (int)tail) {
+                    tv[j] = ld<NT>(ell_val + tb + (size_t)j * kWave);
+                    tc[j] = ld<NT>(a.ell_col + tb + (size_t)j * kWave);
+                }
+#pragma unroll
+            for (int j = 0; j < KC - 1; ++j)
+                if (j < (int)tail) {
+                    const Acc vv = P::value(tv[j]);
+                    const XR xv = xsr[tc[j]];
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k) acc[k] = fma(vv, (Acc)lane_of<X, NRHS>(xv, k), acc[k]);
                 }
         }
 #pragma unroll
@@ -895,7 +920,7 @@ ehyb_status ehyb_batch_create(const ehyb_plan* const* plans, int32_t n_plans, in
             for (int32_t p = 0; p < P.nparts; ++p) {
                 int64_t c = 0;
                 for (int32_t sl = P.slice_start[p]; sl < P.slice_start[p + 1]; ++sl)
-                    c += (int64_t)(P.ell_meta[4 * (size_t)sl + 1] & 0xFFFFu) * kWave * P.kc * (P.vbytes + 2);
+                    c += (int64_t)(P.ell_meta[4 * (size_t)sl + 1] & 0xFFFFu) * kWave * (P.vbytes + 2);
                 for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e)
                     c += (int64_t)P.er_meta[2 * (size_t)e + 1] * kWave * (P.vbytes + 4);
                 c += 2LL * (P.part_start[p + 1] - P.part_start[p]) * P.xbytes * n_rhs;

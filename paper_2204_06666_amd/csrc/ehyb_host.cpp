@@ -285,9 +285,23 @@ using namespace ehyb;
 
 namespace {
 
-inline int64_t ell_slot_of(int64_t off, int32_t k, int32_t r, int L, int kc) {
-    const int64_t t = k / (L * kc), u = (k / kc) % L, c = k % kc;
-    return off + (t * kWave + (int64_t)r * L + u) * kc + c;
+// ELL slot of entry k of row r in a slice with `full` steps of kc entries
+// per lane, followed by single-entry steps.
+inline int64_t ell_slot_of(int64_t off, int32_t k, int32_t r, int L, int kc, int32_t full) {
+    const int64_t kf = (int64_t)full * L * kc;
+    if (k < kf) {
+        const int64_t t = k / (L * kc), u = (k / kc) % L, c = k % kc;
+        return off + (t * kWave + (int64_t)r * L + u) * kc + c;
+    }
+    const int64_t k1 = k - kf;
+    return off + (int64_t)full * kWave * kc + (k1 / L) * kWave + (int64_t)r * L + k1 % L;
+}
+
+// Entries per lane of a slice whose longest row has m ELL entries: whole
+// steps of L*kc entries, then single-entry steps of L entries for the rest.
+inline int64_t ell_width_of(int64_t m, int L, int kc) {
+    const int64_t full = m / (L * kc);
+    return full * kc + (m - full * L * kc + L - 1) / L;
 }
 
 inline int64_t er_slot_of(int64_t off, int32_t k, int32_t r, int L) {
@@ -448,7 +462,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                 return fail(EHYB_EUNSUPPORTED, "more than 65535 row-slices in one partition");
     }
     std::vector<int32_t> slice_part(ns), slice_j(ns);
-    std::vector<int64_t> ell_steps(ns);
+    std::vector<int64_t> ell_steps(ns);  // entries per lane of each slice
     std::vector<uint64_t> er_mask(ns, 0);
     P->ell_free.assign(nparts, 0);
 #pragma omp parallel for schedule(dynamic, 4)
@@ -466,7 +480,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                 if (P->row_er_len[r] > 0) mask |= 1ull << (r - r0);
             }
             mk[j] = mask;
-            st[j] = (me + L * kc - 1) / (L * kc);
+            st[j] = ell_width_of(me, L, kc);
         }
         int32_t at = P->slice_start[p], nfree = 0;
         for (int pass = 0; pass < 2; ++pass)
@@ -485,12 +499,12 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     int64_t eoff = 0;
     for (int32_t s = 0; s < ns; ++s) {
         if (eoff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the ELL part");
-        if (ell_steps[s] > 65535) return fail(EHYB_EUNSUPPORTED, "ELL row-slice wider than 65535 steps");
+        if (ell_steps[s] > 65535) return fail(EHYB_EUNSUPPORTED, "ELL row-slice wider than 65535 entries per lane");
         P->ell_meta[4 * (size_t)s + 0] = (uint32_t)eoff;
         P->ell_meta[4 * (size_t)s + 1] = (uint32_t)ell_steps[s] | ((uint32_t)slice_j[s] << 16);
         P->ell_meta[4 * (size_t)s + 2] = (uint32_t)(er_mask[s] & 0xFFFFFFFFu);
         P->ell_meta[4 * (size_t)s + 3] = (uint32_t)(er_mask[s] >> 32);
-        eoff += ell_steps[s] * kWave * kc;
+        eoff += ell_steps[s] * kWave;
     }
     if (eoff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the ELL part");
     // residual slices
@@ -542,6 +556,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
             const int32_t r0 = ps + slice_j[s] * C;
             const int32_t r1 = std::min(r0 + C, pe);
             const int64_t eo = P->ell_meta[4 * (size_t)s + 0];
+            const int32_t full = (int32_t)(P->ell_meta[4 * (size_t)s + 1] & 0xFFFFu) / kc;
             for (int32_t row = r0; row < r1; ++row) {
                 const int32_t r = row - r0;
                 const int32_t old = P->perm[row];
@@ -568,7 +583,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                         if (f != he && *f == nc) local = (pe - ps) + (int32_t)(f - hb);
                     }
                     if (local >= 0 && k1 < ell_len) {
-                        const int64_t slot = ell_slot_of(eo, k1++, r, L, kc);
+                        const int64_t slot = ell_slot_of(eo, k1++, r, L, kc, full);
                         store_value(&P->ell_val[(size_t)slot * vb], vb, dt, v);
                         P->ell_col[slot] = (uint16_t)local;
                         if (local >= pe - ps) ++nnz_halo;
@@ -841,6 +856,7 @@ ehyb_status ehyb_plan_decode_csr(const ehyb_plan* P, int64_t* row_ptr, int32_t* 
         for (int32_t s = P->slice_start[p]; s < P->slice_start[p + 1]; ++s) {
             const int64_t eo = P->ell_meta[4 * (size_t)s + 0];
             const int32_t r0 = ps + (int32_t)(P->ell_meta[4 * (size_t)s + 1] >> 16) * C;
+            const int32_t full = (int32_t)(P->ell_meta[4 * (size_t)s + 1] & 0xFFFFu) / kc;
             for (int32_t r = 0; r < C && r0 + r < pe; ++r) {
                 const int32_t row = r0 + r;
                 int64_t out_at = row_ptr[row];
@@ -851,7 +867,7 @@ ehyb_status ehyb_plan_decode_csr(const ehyb_plan* P, int64_t* row_ptr, int32_t* 
                 const bool ew = ep >= 0 && (P->er_meta[2 * (size_t)(ep / C) + 1] & kErWide);
                 const int32_t rr = ep >= 0 ? ep % C : 0;
                 while (a < na || b < nb) {
-                    const int64_t sa = a < na ? ell_slot_of(eo, a, r, L, kc) : 0;
+                    const int64_t sa = a < na ? ell_slot_of(eo, a, r, L, kc, full) : 0;
                     const int64_t sb = b < nb ? (ew ? er_slot_of(ro, b, 0, kWave) : er_slot_of(ro, b, rr, L)) : 0;
                     int32_t ca = INT32_MAX;
                     if (a < na) {
@@ -887,13 +903,13 @@ void ehyb_plan_destroy(ehyb_plan* P) { delete P; }
 }  // extern "C"
 
 // ------------------------------------------------------------- plan files
-// Layout: magic "EHYBPLN5", u32 version, then fixed header fields and arrays
+// Layout: magic "EHYBPLN6", u32 version, then fixed header fields and arrays
 // (each prefixed by its u64 byte length), then a u64 FNV-1a checksum of all
 // preceding bytes.
 
 namespace {
-const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '5'};
-const uint32_t kVersion = 5;
+const char kMagic[8] = {'E', 'H', 'Y', 'B', 'P', 'L', 'N', '6'};
+const uint32_t kVersion = 6;
 
 uint64_t fnv1a(const unsigned char* p, size_t n, uint64_t h = 1469598103934665603ull) {
     for (size_t i = 0; i < n; ++i) {
@@ -988,16 +1004,19 @@ const char* validate_loaded(const ehyb_plan& P) {
         if (P.ell_free[p] < 0 || P.ell_free[p] > sl) return "plan file ELL free-slice count is inconsistent";
         std::vector<char> seen_j((size_t)sl, 0);
         for (int32_t s = P.slice_start[p]; s < P.slice_start[p + 1]; ++s) {
-            const uint64_t eo = P.ell_meta[4 * (size_t)s], es = P.ell_meta[4 * (size_t)s + 1] & 0xFFFFu;
+            const uint64_t eo = P.ell_meta[4 * (size_t)s], ew = P.ell_meta[4 * (size_t)s + 1] & 0xFFFFu;
             const int64_t j = P.ell_meta[4 * (size_t)s + 1] >> 16;
             if (j >= sl || seen_j[(size_t)j]) return "plan file ELL slice indices are not a permutation";
             seen_j[(size_t)j] = 1;
-            if (eo + es * kWave * P.kc > (uint64_t)P.ell_slots) return "plan file ELL slot range out of bounds";
+            if (eo + ew * kWave > (uint64_t)P.ell_slots) return "plan file ELL slot range out of bounds";
             const int64_t ext = sz + P.halo_start[p + 1] - P.halo_start[p];
-            for (uint64_t q = eo; q < eo + es * kWave * P.kc; ++q)
+            for (uint64_t q = eo; q < eo + ew * kWave; ++q)
                 if (P.ell_col[q] >= ext) return "plan file ELL column outside its LDS vector";
             const uint64_t mask = (uint64_t)P.ell_meta[4 * (size_t)s + 2] | ((uint64_t)P.ell_meta[4 * (size_t)s + 3] << 32);
             const int64_t rows = std::min<int64_t>(C, sz - j * C);
+            for (int64_t r = 0; r < rows; ++r)
+                if (P.row_ell_len[P.part_start[p] + j * C + r] > (int64_t)ew * P.L)
+                    return "plan file row has more ELL entries than its slice holds";
             if (rows < 64 && (mask >> rows) != 0) return "plan file residual mask names a missing row";
         }
         for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e) {
@@ -1008,6 +1027,8 @@ const char* validate_loaded(const ehyb_plan& P) {
             for (int r = 0; r < C; ++r) {
                 const uint16_t lr = P.er_row[(size_t)e * C + r];
                 if (lr != 0xFFFF && lr >= sz) return "plan file residual row outside its partition";
+                if (lr != 0xFFFF && P.row_er_len[P.part_start[p] + lr] > (int64_t)rs * (wide ? kWave : P.L))
+                    return "plan file row has more residual entries than its slice holds";
                 if (wide && (r == 0) != (lr != 0xFFFF)) return "plan file wide residual slice must hold one row";
             }
         }

@@ -35,7 +35,7 @@ def _tiny():
                 slice_start=np.array([0, 1, 2]), er_slice_start=np.array([0, 1, 2]),
                 ell_free=np.array([0, 0]), halo_start=np.array([0, 0, 0]),
                 halo_idx=np.zeros(0, dtype=np.int32),
-                ell_meta=np.array([[0, 1, 0b01, 0], [128, 1, 0b10, 0]], dtype=np.uint32),
+                ell_meta=np.array([[0, 2, 0b01, 0], [128, 2, 0b10, 0]], dtype=np.uint32),
                 er_meta=np.array([[0, 1], [64, 1]], dtype=np.uint32), er_row=er_row,
                 ell_val=ell_val, ell_col=ell_col, er_val=er_val, er_col=er_col,
                 row_ell_len=np.array([2, 2, 2, 2]), row_er_len=np.array([1, 0, 0, 1]))
@@ -89,6 +89,49 @@ def test_intra_partition_entry_in_residual_is_caught():
     # a width cap of 1 would need every ELL row to respect it, which rows 0, 2, 3 do not
     with pytest.raises(PlanError):
         check_plan(A, view, width_cap=1)
+
+
+def _tail():
+    """One partition of three rows with 3, 2 and 1 entries, one lane per row,
+    two entries per full step: width 3 = one full step (slots 0..127, lane r
+    at 2r, 2r+1) and one single-entry step (slots 128..191, lane r at 128+r)."""
+    d = np.array([[1, 2, 3], [4, 5, 0], [0, 0, 6]], dtype=np.float64)
+    A = matgen.from_dense(d)
+    ell_val = np.zeros(192)
+    ell_col = np.zeros(192, dtype=np.uint16)
+    for slot, v, c in [(0, 1, 0), (1, 2, 1), (128, 3, 2), (2, 4, 0), (3, 5, 1), (4, 6, 2)]:
+        ell_val[slot], ell_col[slot] = v, c
+    er_row = np.zeros((0, 64), dtype=np.uint16)
+    view = dict(n=3, nparts=1, L=1, kc=2, perm=np.arange(3), part_start=np.array([0, 3]),
+                slice_start=np.array([0, 1]), er_slice_start=np.array([0, 0]),
+                ell_free=np.array([1]), halo_start=np.array([0, 0]), halo_idx=np.zeros(0, dtype=np.int32),
+                ell_meta=np.array([[0, 3, 0, 0]], dtype=np.uint32),
+                er_meta=np.zeros((0, 2), dtype=np.uint32), er_row=er_row,
+                ell_val=ell_val, ell_col=ell_col, er_val=np.zeros(0), er_col=np.zeros(0, dtype=np.int32),
+                row_ell_len=np.array([3, 2, 1]), row_er_len=np.array([0, 0, 0]))
+    return A, d, view
+
+
+def test_single_entry_steps_after_full_steps():
+    A, d, view = _tail()
+    st = check_plan(A, view)
+    assert st["ell_slots"] == 192 and st["nnz_ell"] == 6
+    x = np.array([1.0, -2.0, 0.5])
+    assert np.array_equal(layout_spmv(view, x), d @ x)
+
+
+@pytest.mark.parametrize("mutate", [
+    lambda v: v["ell_meta"].__setitem__((0, 1), 4),                  # wider than the longest row needs
+    lambda v: v["ell_meta"].__setitem__((0, 1), 2),                  # too narrow for row 0
+    lambda v: (v["ell_val"].__setitem__(128, 0.0), v["ell_val"].__setitem__(2 * 0 + 2, 3.0)),
+    lambda v: (v["ell_val"].__setitem__(128, 0.0), v["ell_val"].__setitem__(129, 3.0),
+               v["ell_col"].__setitem__(129, 2)),                    # entry 2 of row 0 in lane 1
+])
+def test_single_entry_step_mistakes_are_caught(mutate):
+    A, _, view = _tail()
+    mutate(view)
+    with pytest.raises((PlanError, IndexError, ValueError)):
+        check_plan(A, view)
 
 
 def test_lds_budget_and_16bit_limit():
