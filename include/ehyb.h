@@ -102,8 +102,9 @@ typedef struct {
                                At most lds_bytes/tau and 65536 rows. */
     int32_t ell_width_cap;  /* max ELL entries per row: > 0 as given; -1 =
                                unlimited (the paper's split by partition
-                               only; a row-slice wider than 65535 entries per
-                               lane is EHYB_EUNSUPPORTED); 0 = automatic, 128 load steps per lane
+                               only; a row-slice wider than 65535 entries
+                               per lane is EHYB_EUNSUPPORTED); 0 = automatic,
+                               128 load steps per lane
                                group (128 * lanes per row * kc entries), which
                                only hub rows reach: their excess entries go
                                to the residual part, where they run on wide
@@ -186,8 +187,9 @@ typedef struct {
  * row r of the slice is local row j*C + r); a 64-bit mask (low word, high
  * word) whose bit r says that row r also has residual entries.  A slice of
  * width W holds 64*W slots: W / KC steps of KC entries per lane, then
- * W % KC single-entry steps, so a row of m ELL entries needs W = (m / (L*KC))*KC
- * + ceil((m mod L*KC) / L), with no padding beyond the longest row.  Columns are 16-bit indices into the
+ * W % KC single-entry steps, so a row of m ELL entries needs
+ * W = (m / (L*KC))*KC + ceil((m mod L*KC) / L), with no padding beyond the
+ * slice's longest row.  Columns are 16-bit indices into the
  * partition's LDS vector: c < size of the partition is x-slice element c
  * (permuted row part_start[p] + c); c >= size is halo element
  * halo_idx[halo_start[p] + c - size].
