@@ -102,9 +102,7 @@ typedef struct {
                                At most lds_bytes/tau and 65536 rows. */
     int32_t ell_width_cap;  /* max ELL entries per row: > 0 as given; -1 =
                                unlimited (the paper's split by partition
-                               only; a row-slice wider than 65535 entries
-                               per lane is EHYB_EUNSUPPORTED); 0 = automatic,
-                               128 load steps per lane
+                               only); 0 = automatic, 128 load steps per lane
                                group (128 * lanes per row * kc entries), which
                                only hub rows reach: their excess entries go
                                to the residual part, where they run on wide
