@@ -54,6 +54,39 @@ def test_config1_parity(torch, rpw, permuted, halo):
     _check(A, x, y, f"cfg1 rpw={rpw} permuted={permuted}")
 
 
+def _long_wide_slices(P, threshold=32):
+    """Wide residual slices (one row on 64 lanes) longer than `threshold` steps."""
+    m = np.asarray(P.arrays()["er_meta"]).reshape(-1, 2).astype(np.int64)
+    return int((((m[:, 1] >> 31) == 1) & ((m[:, 1] & 0x7FFFFFFF) > threshold)).sum())
+
+
+@pytest.mark.parametrize("rpw,halo", [(64, 0), (16, -1), (4, 0), (64, -1)])
+def test_long_hub_rows(torch, rpw, halo):
+    """Residual rows of 10^4 entries (wide slices of hundreds of steps):
+    parity with the oracle, and the same bits on every launch."""
+    A = matgen.powerlaw(60000, exponent=2.2, mean_deg=30, seed=5)
+    x = matgen.uniform_vector(A.n_rows, 6)
+    y, P = _ehyb(torch, A, x, rows_per_wave=rpw, halo_rows=halo, slice_rows=2000)
+    n_long = _long_wide_slices(P)
+    assert n_long > 0
+    _check(A, x, y, f"long hub rows rpw={rpw} halo={halo} long wide slices={n_long}")
+    xp = _dev(torch, x[P.perm()])
+    first = P.spmv(xp).clone()
+    for _ in range(5):
+        assert torch.equal(P.spmv(xp).view(torch.int64), first.view(torch.int64))
+
+
+def test_long_hub_rows_integer_exact(torch):
+    """Integer values and x: every partial sum is exact, so the product
+    equals the oracle bit for bit."""
+    A = matgen.powerlaw(60000, exponent=2.2, mean_deg=30, seed=5)
+    A = matgen.Csr(A.n_rows, A.n_cols, A.row_ptr, A.col, np.rint(A.val * 8.0))
+    x = matgen.integer_vector(A.n_rows, 19, bound=1 << 10)
+    y, P = _ehyb(torch, A, x, rows_per_wave=16, halo_rows=-1, slice_rows=2000)
+    assert _long_wide_slices(P) > 0
+    assert np.array_equal(y, oracle.spmv(A, x))
+
+
 @pytest.mark.parametrize("rpw,halo", [(64, 0), (8, -1), (64, -1)])
 def test_integer_poisson_bit_exact(torch, rpw, halo):
     A = matgen.config_matrix(1)
