@@ -166,7 +166,9 @@ typedef struct {
     int32_t n_rhs;            /* right-hand sides the plan is sized for */
     int32_t n_er_wide;        /* wide residual slices (one long row, 64 lanes) */
     int32_t ell_width_cap;    /* ELL width cap in effect, 0 = none */
-    int32_t reserved3;
+    int32_t n_er_pieces;      /* pieces of at most 16 steps the wide residual
+                                 slices are summed in by ehyb_spmv (0 = no
+                                 wide slices) */
     double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */
 } ehyb_plan_stats;
 
@@ -265,8 +267,10 @@ EHYB_API ehyb_status ehyb_plan_arrays_get(const ehyb_plan *plan, ehyb_plan_array
 EHYB_API ehyb_status ehyb_plan_decode_csr(const ehyb_plan *plan, int64_t *row_ptr, int32_t *col_idx,
                                  double *val);
 
-/* Bytes of device memory the plan needs (metadata, both parts, permutation
- * and two n-vectors of scratch for unpermuted calls), 256-byte aligned. */
+/* Bytes of device memory the plan needs (metadata, both parts, permutation,
+ * two n-vectors of scratch for unpermuted calls and, when the plan has wide
+ * residual slices, their piece list and one 8-byte partial sum per piece),
+ * 256-byte aligned. */
 EHYB_API ehyb_status ehyb_plan_device_bytes(const ehyb_plan *plan, size_t *bytes);
 
 /* Copy the plan into `dev_blob` (device, at least device_bytes bytes,
@@ -277,9 +281,13 @@ EHYB_API ehyb_status ehyb_plan_upload(ehyb_plan *plan, void *dev_blob, size_t by
 
 /* y = A x on the device (Alg. 3).  x, y: device FP64 vectors of length n for
  * FP64 plans.  With EHYB_VEC_PERMUTED they are in permuted order; otherwise in
- * the original order.  Launches on one plan blob must not overlap in time when
- * the unpermuted mode is used (they share its scratch vectors).  Every row of
- * y is overwritten; the result is bitwise deterministic. */
+ * the original order.  A plan with wide residual slices (hub rows, see
+ * n_er_pieces) first sums them in pieces over the whole device (the global
+ * residual queue of Alg. 3, for these rows only), one more launch on the same
+ * stream; each partition then adds its rows' pieces in a fixed order.
+ * Launches on one plan blob must not overlap in time when the unpermuted mode
+ * is used or the plan has wide residual slices (they share its scratch).
+ * Every row of y is overwritten; the result is bitwise deterministic. */
 EHYB_API ehyb_status ehyb_spmv(const ehyb_plan *plan, const void *x, void *y, uint32_t flags,
                       void *stream);
 

@@ -39,7 +39,7 @@ class PlanStats(ctypes.Structure):
                 ("max_part_rows", c_i32), ("rows_per_slice", c_i32), ("lanes_per_row", c_i32),
                 ("kc", c_i32), ("value_dtype", c_i32), ("eq1_K", c_i32),
                 ("max_halo", c_i32), ("lds_bytes_used", c_i32), ("n_rhs", c_i32), ("n_er_wide", c_i32),
-                ("ell_width_cap", c_i32), ("reserved3", c_i32),
+                ("ell_width_cap", c_i32), ("n_er_pieces", c_i32),
                 ("t_graph_s", ctypes.c_double), ("t_partition_s", ctypes.c_double),
                 ("t_reorder_s", ctypes.c_double), ("t_encode_s", ctypes.c_double)]
 

@@ -33,9 +33,14 @@ struct PartArrays {
     const int32_t* ell_free;        // [nparts] leading ELL slices without residual rows
     const int32_t* halo_start;      // [nparts+1]
     const int32_t* halo_idx;        // cached neighbour x entries (permuted indices)
-    const uint4* ell_meta;          // slot offset, steps | index << 16, residual-row mask (lo, hi)
+    const uint4* ell_meta;          // slot offset, width | index << 16, residual-row mask (lo, hi)
     const uint2* er_meta;           // slot offset, steps
     const uint16_t* er_row;         // local row of each residual slice row, 0xFFFF = none
+    // Wide residual slices summed beforehand (ehyb_spmv, one right-hand side):
+    // slice e's pieces are er_piece[e] .. er_piece[e+1]-1, their sums in
+    // er_part.  Null: every slice is summed by its partition's workgroup.
+    const int32_t* er_piece;
+    const void* er_part;
     const void* ell_val;            // value type of the plan
     const uint16_t* ell_col;
     const void* er_val;
@@ -63,6 +68,8 @@ PartArrays part_arrays(const ehyb_plan& P) {
     a.er_col = (const int32_t*)(blob + Ly.er_col);
     a.lds_rows = P.max_part_rows + P.max_halo;
     a.n = (int32_t)P.n;
+    a.er_piece = nullptr;
+    a.er_part = nullptr;
     return a;
 }
 
@@ -384,6 +391,21 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
             const V* ev = er_val + off + lane;
             const int32_t* ec = a.er_col + off + lane;
             const uint16_t lr = a.er_row[(size_t)(e0 + it) * C + (wide ? 0 : r)];
+            if constexpr (NRHS == 1) {
+                if (wide && a.er_piece != nullptr) {
+                    // summed beforehand in pieces: add them in piece order
+                    const int q0 = __builtin_amdgcn_readfirstlane(a.er_piece[e0 + it]);
+                    const int q1 = __builtin_amdgcn_readfirstlane(a.er_piece[e0 + it + 1]);
+                    const Acc* part = static_cast<const Acc*>(a.er_part);
+                    Acc sum = 0;
+                    for (int q = q0; q < q1; ++q) sum += part[q];
+                    if (lane == 0 && lr != 0xFFFF) yer[lr] = sum;
+                    wave_signal(&Q.n_er_done, lane);
+                    it = itn;
+                    m = mn;
+                    continue;
+                }
+            }
             Acc acc[NRHS];
 #pragma unroll
             for (int k = 0; k < NRHS; ++k) acc[k] = 0;
@@ -562,6 +584,69 @@ __global__ void __launch_bounds__(1024) ehyb_spmm_batched_kernel(BatchArgs args)
         __hip_atomic_store(&counters[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_store(&counters[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+}
+
+// The wide residual slices of ehyb_spmv (one right-hand side), summed before
+// the product over the whole device: one wavefront per piece of at most
+// kPieceSteps steps.  Entry k of a wide slice is at slot off + k, so piece
+// (e, t0, t1) holds slots off + 64*t0 .. off + 64*t1 - 1, one per lane per
+// step; each lane sums its entries in step order, then the wavefront adds
+// its lanes in a fixed tree.  The partition's workgroup adds the pieces of
+// its row in piece order, so results do not depend on timing.
+template <int DT, bool NT>
+__global__ void __launch_bounds__(256) er_pieces_kernel(const uint2* __restrict__ er_meta,
+                                                        const void* __restrict__ er_val_,
+                                                        const int32_t* __restrict__ er_col,
+                                                        const int32_t* __restrict__ pieces, int n_pieces,
+                                                        const void* __restrict__ x_, void* __restrict__ part_) {
+    using P = Prec<DT>;
+    using V = typename P::V;
+    using X = typename P::X;
+    using Acc = typename P::A;
+    const V* er_val = static_cast<const V*>(er_val_);
+    const X* x = static_cast<const X*>(x_);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int q = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (q >= n_pieces) return;
+    const int e = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q]);
+    const int t0 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 1]);
+    const int t1 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 2]);
+    const size_t base = (size_t)__builtin_amdgcn_readfirstlane(er_meta[e].x) + lane;
+    int32_t c[kPieceSteps];
+    V v[kPieceSteps];
+#pragma unroll
+    for (int j = 0; j < kPieceSteps; ++j)
+        if (t0 + j < t1) {
+            c[j] = ld<NT>(er_col + base + (size_t)(t0 + j) * kWave);
+            v[j] = ld<NT>(er_val + base + (size_t)(t0 + j) * kWave);
+        }
+    X xg[kPieceSteps];
+#pragma unroll
+    for (int j = 0; j < kPieceSteps; ++j)
+        if (t0 + j < t1) xg[j] = x[c[j]];
+    Acc acc = 0;
+#pragma unroll
+    for (int j = 0; j < kPieceSteps; ++j)
+        if (t0 + j < t1) acc = fma(P::value(v[j]), (Acc)xg[j], acc);
+    acc = reduce_lanes<kWave>(acc);
+    if (lane == 0) static_cast<Acc*>(part_)[q] = acc;
+}
+
+template <int DT>
+void launch_pieces(const ehyb_plan& P, bool nt, const void* x, hipStream_t s) {
+    const char* blob = (const char*)P.dev_blob;
+    const BlobLayout& Ly = P.layout;
+    const int nblocks = (P.n_pieces + 3) / 4;  // four wavefronts per 256-thread workgroup
+    const uint2* meta = (const uint2*)(blob + Ly.er_meta);
+    const int32_t* col = (const int32_t*)(blob + Ly.er_col);
+    const int32_t* pc = (const int32_t*)(blob + Ly.pieces);
+    void* part = (void*)(blob + Ly.ypart);
+    if (nt)
+        hipLaunchKernelGGL((er_pieces_kernel<DT, true>), dim3(nblocks), dim3(256), 0, s, meta, blob + Ly.er_val, col, pc,
+                           P.n_pieces, x, part);
+    else
+        hipLaunchKernelGGL((er_pieces_kernel<DT, false>), dim3(nblocks), dim3(256), 0, s, meta, blob + Ly.er_val, col,
+                           pc, P.n_pieces, x, part);
 }
 
 // Plain CSR SpMV: L lanes per row (rows of a wavefront are consecutive),
@@ -774,6 +859,8 @@ ehyb_status ehyb_plan_upload(ehyb_plan* P, void* dev_blob, size_t bytes, void* s
         {L.er_val, P->er_val.data(), P->er_val.size()},
         {L.er_col, P->er_col.data(), P->er_col.size() * 4},
         {L.perm, P->perm.data(), P->perm.size() * 4},
+        {L.piece_start, P->piece_start.data(), P->piece_start.size() * 4},
+        {L.pieces, P->pieces.data(), P->pieces.size() * 4},
     };
     for (const Piece& pc : pieces) {
         if (pc.bytes == 0) continue;
@@ -871,6 +958,19 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     if (P->kc != kc_for(P->value_dtype)) return fail(EHYB_EINVAL, "plan chunk width does not match its value type");
     const int threads = launch_waves(*P) * kWave;
     const bool nt = use_stream_loads(P->load_mode, algorithmic_bytes(*P));
+    if (P->n_pieces > 0) {
+        // hub rows: their wide residual slices are summed first, over the whole device
+        switch (P->value_dtype) {
+            case EHYB_F64: launch_pieces<EHYB_F64>(*P, nt, xin, s); break;
+            case EHYB_F32: launch_pieces<EHYB_F32>(*P, nt, xin, s); break;
+            case EHYB_BF16: launch_pieces<EHYB_BF16>(*P, nt, xin, s); break;
+            case EHYB_F32_ACC64: launch_pieces<EHYB_F32_ACC64>(*P, nt, xin, s); break;
+            case EHYB_BF16_ACC64: launch_pieces<EHYB_BF16_ACC64>(*P, nt, xin, s); break;
+            default: return fail(EHYB_EINVAL, "bad value type");
+        }
+        a.m.er_piece = (const int32_t*)(blob + Ly.piece_start);
+        a.m.er_part = blob + Ly.ypart;
+    }
     bool ok = false;
     switch (P->value_dtype) {
         case EHYB_F64: ok = launch_spmv_dt<EHYB_F64>(P->L, nt, a, nblocks, threads, lds, s); break;

@@ -227,6 +227,8 @@ int64_t algorithmic_bytes(const ehyb_plan& p) {
     b += (int64_t)p.halo_idx.size() * 4;                         // halo indices
     b += p.n * p.xbytes;                               // x, each element once (slice staging)
     b += p.n * p.xbytes;                               // y, written once
+    if (p.n_pieces > 0)                                // wide slices in pieces: piece list,
+        b += (int64_t)(p.ner_slices + 1) * 4 + (int64_t)p.n_pieces * (12 + 2 * 8);  // partial sums out and in
     return b;
 }
 
@@ -254,6 +256,11 @@ BlobLayout compute_layout(const ehyb_plan& p) {
     L.perm = take((size_t)p.n * 4);
     L.xp = take((size_t)p.n * p.xbytes);
     L.yp = take((size_t)p.n * p.xbytes);
+    if (p.n_pieces > 0) {
+        L.piece_start = take((size_t)(p.ner_slices + 1) * 4);
+        L.pieces = take((size_t)p.n_pieces * 12);
+        L.ypart = take((size_t)p.n_pieces * 8);
+    }
     L.total = off == 0 ? kBlobAlign : off;
     return L;
 }
@@ -266,6 +273,29 @@ int64_t lds_bytes_used(const ehyb_plan& p, int n_rhs) {
     const int64_t ab = acc_bytes(p.value_dtype);
     const int64_t acc = p.ner_slices > 0 ? (int64_t)p.max_part_rows * ab * n_rhs : 0;
     return (acc > 0 ? (xs + ab - 1) / ab * ab : xs) + acc;
+}
+
+// Pieces of the wide residual slices: slice e of S steps is cut into
+// ceil(S / kPieceSteps) pieces of consecutive steps, in slice order.
+void build_pieces(ehyb_plan& P) {
+    P.piece_start.assign((size_t)P.ner_slices + 1, 0);
+    P.pieces.clear();
+    int32_t q = 0;
+    for (int32_t e = 0; e < P.ner_slices; ++e) {
+        P.piece_start[e] = q;
+        const uint32_t m = P.er_meta[2 * (size_t)e + 1];
+        if (!(m & kErWide)) continue;
+        const int32_t steps = (int32_t)(m & ~kErWide);
+        for (int32_t t = 0; t < steps; t += kPieceSteps) {
+            P.pieces.push_back(e);
+            P.pieces.push_back(t);
+            P.pieces.push_back(std::min(steps, t + kPieceSteps));
+            ++q;
+        }
+    }
+    P.piece_start[P.ner_slices] = q;
+    P.n_pieces = q;
+    if (q == 0) P.piece_start.clear();
 }
 
 // Residual position of every permuted row (e*C + r, or -1), from er_row.
@@ -537,6 +567,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     if (roff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the residual part");
     P->ell_slots = eoff;
     P->er_slots = roff;
+    build_pieces(*P);
     const int vb = P->vbytes, dt = P->value_dtype;
     P->ell_val.assign((size_t)eoff * vb, 0);   // +0.0 padding in every value type
     P->ell_col.assign((size_t)eoff, 0);
@@ -787,6 +818,7 @@ ehyb_status ehyb_plan_stats_get(const ehyb_plan* P, ehyb_plan_stats* out) {
     out->er_slots = P->er_slots;
     out->n_er_rows = P->n_er_rows;
     out->n_er_wide = P->n_er_wide;
+    out->n_er_pieces = P->n_pieces;
     out->ell_width_cap = P->params.ell_width_cap;
     out->nnz_halo = P->nnz_halo;
     out->n_halo = (int64_t)P->halo_idx.size();
@@ -1177,6 +1209,7 @@ ehyb_status ehyb_plan_load(const char* path, ehyb_plan** out) {
         P->iperm.resize((size_t)P->n);
         for (size_t i = 0; i < (size_t)P->n; ++i) P->iperm[P->perm[i]] = (int32_t)i;
         build_er_pos(*P);
+        build_pieces(*P);
         P->n_er_wide = 0;
         for (int32_t e = 0; e < P->ner_slices; ++e) P->n_er_wide += (P->er_meta[2 * (size_t)e + 1] & kErWide) != 0;
         *out = P.release();

@@ -41,6 +41,10 @@ constexpr int kWideSteps = 32;
 // steps of one row (256 FP64 entries per lane at one lane per row).
 constexpr int kAutoCapSteps = 128;
 constexpr uint32_t kErWide = 1u << 31;
+// ehyb_spmv sums every wide residual slice before the product, spread over
+// the whole device in pieces of at most kPieceSteps steps (one wavefront
+// each); the partition's workgroup then adds its row's pieces in order.
+constexpr int kPieceSteps = 16;
 
 // Allocator whose resize() leaves new elements uninitialised, so that large
 // arrays filled by parallel loops are not first zeroed by one thread.
@@ -94,6 +98,7 @@ struct BlobLayout {
     size_t ell_meta = 0, er_meta = 0, er_row = 0;
     size_t ell_val = 0, ell_col = 0, er_val = 0, er_col = 0;
     size_t perm = 0, xp = 0, yp = 0;
+    size_t piece_start = 0, pieces = 0, ypart = 0;  // wide residual slices in pieces
     size_t total = 0;
 };
 
@@ -126,6 +131,11 @@ struct ehyb_plan {
     std::vector<unsigned char> er_val;    // er_slots * vbytes
     std::vector<int32_t> er_col;          // er_slots
     std::vector<int32_t> row_ell_len, row_er_len;  // [n], permuted rows
+    // pieces of the wide residual slices (derived from er_meta): piece_start
+    // [ner_slices+1] gives each slice's first piece (none for other slices),
+    // pieces [3*n_pieces] = (slice, first step, end step)
+    std::vector<int32_t> piece_start, pieces;
+    int32_t n_pieces = 0;
     int64_t ell_slots = 0, er_slots = 0;
     int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0, nnz_halo = 0;
     int32_t n_er_wide = 0;                // residual slices processed by all 64 lanes

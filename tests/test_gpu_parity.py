@@ -76,6 +76,40 @@ def test_long_hub_rows(torch, rpw, halo):
         assert torch.equal(P.spmv(xp).view(torch.int64), first.view(torch.int64))
 
 
+def test_long_hub_rows_unpermuted_and_graph_replays(torch):
+    """Hub rows (wide slices summed in pieces by a launch before the product)
+    with vectors in the original order, and both launches recorded in a HIP
+    graph: every replay, with new x between replays, equals an eager call."""
+    A = matgen.powerlaw(30000, exponent=2.1, mean_deg=20, seed=9)
+    x = matgen.uniform_vector(A.n_rows, 10)
+    P = Plan(A, slice_rows=1500, halo_rows=-1, rows_per_wave=16).upload("cuda:0")
+    assert P.stats()["n_er_pieces"] > 0
+    xd = _dev(torch, x)
+    y = P.spmv(xd, permuted=False)
+    torch.cuda.synchronize()
+    _check(A, x, y.cpu().numpy(), "hub rows, original order")
+    xp = _dev(torch, x[P.perm()])
+    yp = torch.empty_like(xp)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        P.spmv(xp, yp, stream=s)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        P.spmv(xp, yp, stream=s)
+    ye = torch.empty_like(yp)
+    rng = matgen.rng(12)
+    for rep in range(4):
+        xp.copy_(torch.from_numpy(rng.uniform(-1, 1, A.n_rows)).to(xp))
+        g.replay()
+        torch.cuda.synchronize()
+        P.spmv(xp, ye)
+        torch.cuda.synchronize()
+        assert torch.equal(yp.view(torch.int64), ye.view(torch.int64)), f"replay {rep}"
+
+
 def test_long_hub_rows_integer_exact(torch):
     """Integer values and x: every partial sum is exact, so the product
     equals the oracle bit for bit."""

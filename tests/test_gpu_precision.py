@@ -129,7 +129,10 @@ def test_low_precision_deterministic(dt):
 def test_acc64_keeps_long_rows_accurate(rpw):
     """Rows of ~1800 entries: with binary64 accumulation the result is the
     binary32 rounding of the exact product of the stored values and x (error
-    at most 2^-24 of sum |a_q x_q|); binary32 accumulation is measurably worse."""
+    at most 2^-24 of sum |a_q x_q|); binary32 accumulation is measurably worse
+    (by less than a plain running sum would be: the residual part of these
+    rows is summed in pieces of at most 1024 entries, which blocks the
+    accumulation)."""
     g = matgen.rng(77)
     n = 2000
     dense = g.uniform(-1, 1, (n, n)) * (g.random((n, n)) < 0.9)
@@ -146,4 +149,4 @@ def test_acc64_keeps_long_rows_accurate(rpw):
     print(f"[precision] long rows rpw={rpw}: binary32 accumulation {errs[EHYB_F32]:.2e}, "
           f"binary64 {errs[EHYB_F32_ACC64]:.2e}", flush=True)
     assert errs[EHYB_F32_ACC64] <= 2.0 ** -24 * 1.001
-    assert errs[EHYB_F32] > 4 * errs[EHYB_F32_ACC64]
+    assert errs[EHYB_F32] > 2 * errs[EHYB_F32_ACC64]

@@ -390,3 +390,22 @@ def test_acc64_plans_size_lds_for_8_byte_accumulators():
     st = P.stats()
     assert st["lds_bytes_used"] <= 160 * 1024 - 64
     _full_check(A, P, value_dtype="bf16", x_bytes=4, acc_bytes=8)
+
+
+def test_wide_slice_pieces(tmp_path):
+    """ehyb_spmv sums each wide residual slice in pieces of at most 16 steps:
+    their number follows from the slices' step counts, survives a plan file,
+    and is zero for a plan without wide slices."""
+    A = matgen.powerlaw(20000, exponent=2.2, mean_deg=20, seed=8)
+    P = Plan(A, slice_rows=1000, halo_rows=-1, rows_per_wave=16)
+    st = P.stats()
+    m = np.asarray(P.arrays()["er_meta"]).reshape(-1, 2).astype(np.int64)
+    wide = (m[:, 1] >> 31) == 1
+    steps = m[:, 1] & 0x7FFFFFFF
+    assert st["n_er_wide"] == int(wide.sum()) > 0
+    assert st["n_er_pieces"] == int((-(-steps[wide] // 16)).sum())
+    assert st["n_er_pieces"] > st["n_er_wide"]
+    f = str(tmp_path / "p.bin")
+    P.save(f)
+    assert Plan.load(f).stats()["n_er_pieces"] == st["n_er_pieces"]
+    assert Plan(matgen.stencil3d(12, perm_seed=1, val_seed=2)).stats()["n_er_pieces"] == 0
