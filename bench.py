@@ -103,11 +103,13 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall-clock budget of the CPU oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "knn-fem", "batched", "predictor"],
+    ap.add_argument("--workload", default="stencil27",
+                    choices=["stencil27", "knn-fem", "batched", "predictor", "powerlaw"],
                     help="stencil27: the headline FP64 product (default); knn-fem: the "
                          "unstructured-FEM matrix in FP64, FP32 and BF16 values; batched: 64 "
                          "uneven FP32 matrices x 8 right-hand sides in one launch; predictor: the "
-                         "learned preprocessing parameters on held-out matrices")
+                         "learned preprocessing parameters on held-out matrices; powerlaw: "
+                         "power-law graphs with hub rows against plain CSR")
     ap.add_argument("--count", type=int, default=64, help="batched only: number of matrices")
     ap.add_argument("--lds-bytes", type=int, default=None,
                     help="batched only: LDS budget per partition (default: the autotuner's choice)")
@@ -127,6 +129,8 @@ def main():
         return run_batched(args)
     if args.workload == "predictor":
         return run_predictor(args)
+    if args.workload == "powerlaw":
+        return run_powerlaw(args)
 
     import numpy as np
     import torch
@@ -549,6 +553,62 @@ def run_batched(args):
         "max_row_scaled_error_vs_quantized": worst,
         "preprocess_s": round(t_pre, 1),
     }
+    print(json.dumps(out), flush=True)
+
+
+def run_powerlaw(args):
+    """Power-law graphs (Chung-Lu) with hub rows of 10^4 entries, default
+    plans, FP64 and FP32 values: EHYB (hub rows summed over the whole device
+    before the product) against the plain CSR kernel on the same GPU, each
+    checked against scipy's FP64 product."""
+    import numpy as np
+    import torch
+
+    import matgen
+    from paper_2204_06666_amd import EHYB_F32, EHYB_F64, Plan, csr_spmv
+
+    dev = torch.device("cuda:0")
+    cases = [("n=6e4 exponent 2.2 mean degree 30", dict(n=60000, exponent=2.2, mean_deg=30, seed=5)),
+             ("n=2.5e5 exponent 2.1 mean degree 40", dict(n=250000, exponent=2.1, mean_deg=40, seed=7))]
+    res = []
+    for desc, kw in cases:
+        log(f"generating power-law {desc}")
+        A = matgen.powerlaw(**kw)
+        x = matgen.uniform_vector(A.n_rows, 3)
+        y64, s64 = fp64_products(A.row_ptr, A.col, A.val, x)
+        rp = torch.from_numpy(A.row_ptr.astype(np.int32)).to(dev)
+        ci = torch.from_numpy(A.col).to(dev)
+        cv = torch.from_numpy(A.val).to(dev)
+        xo = torch.from_numpy(x).to(dev)
+        yo = torch.empty_like(xo)
+        csr = {lanes: time_launches(torch, lambda: csr_spmv(rp, ci, cv, xo, yo, lanes), args.steps, args.warmup)[0]
+               for lanes in (4, 8, 16, 32)}
+        row = {"matrix": desc, "n": int(A.n_rows), "nnz": int(A.nnz),
+               "max_row": int(np.diff(A.row_ptr).max()),
+               "csr_best_us": round(min(csr.values()) * 1e6, 2)}
+        for name, dt in (("f64", EHYB_F64), ("f32", EHYB_F32)):
+            t0 = time.perf_counter()
+            plan = Plan(A, value_dtype=dt).upload(dev)
+            t_pre = time.perf_counter() - t0
+            st = plan.stats()
+            xp = torch.from_numpy(x[plan.perm()].astype(np.float64 if dt == EHYB_F64 else np.float32)).to(dev)
+            yp = torch.empty_like(xp)
+            wall, _ = time_launches(torch, lambda: plan.spmv(xp, yp), args.steps, args.warmup)
+            y = np.empty(A.n_rows)
+            y[plan.perm()] = yp.cpu().numpy()
+            row[name] = {"us": round(wall * 1e6, 2), "GFLOPs": round(2.0 * A.nnz / wall / 1e9, 2),
+                         "nparts": st["nparts"], "nnz_er": st["nnz_er"], "n_er_wide": st["n_er_wide"],
+                         "n_er_pieces": st["n_er_pieces"], "preprocess_s": round(t_pre, 2),
+                         "max_row_scaled_error_vs_fp64": float(scaled_error(y, y64, s64).max())}
+            del plan, xp, yp
+        row["speedup_f64_vs_csr"] = round(row["csr_best_us"] / row["f64"]["us"], 2)
+        log(f"{row}")
+        res.append(row)
+    out = {"metric": "EHYB SpMV on power-law graphs with hub rows, us per product", "value": res[-1]["f64"]["us"],
+           "unit": "us", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(res[-1]["f64"]["us"] / 1e3, 5), "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "Chung-Lu power-law graphs, default plans"}, "matrices": res}
     print(json.dumps(out), flush=True)
 
 
