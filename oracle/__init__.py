@@ -10,7 +10,6 @@ Contents (each follows the passage cited in its docstring):
 * ``spmv``        O1, plain FP64 CSR product (C, ``spmv_ref.c``), y = A x.
 * ``abs_scale``   s_i = sum_j |a_ij||x_j|, the scale of the per-row error bound.
 * ``spmm``        O1 applied to several right-hand sides at once.
-* ``spmv_dense``  dense brute-force product (numpy matmul) for tiny matrices.
 * ``spmv_exact``  exact rational product (``fractions``) for tiny matrices.
 * ``permute``     O2, B = P A P^T for a new->old permutation.
 * ``eq1_rule``    Eq. 1 / Eq. 2, the number of partitions and vector-cache size.
@@ -20,7 +19,6 @@ Contents (each follows the passage cited in its docstring):
 from __future__ import annotations
 
 import ctypes
-import math
 import os
 import subprocess
 from fractions import Fraction
@@ -119,14 +117,6 @@ def spmm(A, X: np.ndarray, threads: int = 0) -> np.ndarray:
     return Y
 
 
-def spmv_dense(A, x: np.ndarray) -> np.ndarray:
-    """Brute force: densify A and use numpy's matrix-vector product."""
-    d = np.zeros((A.n_rows, A.n_cols))
-    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
-    d[rows, A.col] = A.val
-    return d @ np.asarray(x, dtype=np.float64)
-
-
 def spmv_exact(A, x: np.ndarray) -> list:
     """Exact rational y = A x (every binary64 value is a dyadic rational)."""
     xf = [Fraction(float(t)) for t in x]
@@ -137,13 +127,6 @@ def spmv_exact(A, x: np.ndarray) -> list:
             s += Fraction(float(A.val[p])) * xf[int(A.col[p])]
         out.append(s)
     return out
-
-
-def gamma(m: int) -> float:
-    """gamma_m = m u / (1 - m u), u = 2^-53: the classical bound on the relative
-    error of an m-term recursive dot product."""
-    u = 2.0 ** -53
-    return m * u / (1.0 - m * u)
 
 
 def permute(A, perm: np.ndarray):
@@ -211,8 +194,3 @@ def assert_close(y, yref, s, tol: float = 1e-12, what: str = "") -> float:
             f"{what}: row {i} scaled error {e[i]:.3e} > {tol:.1e} "
             f"(y={y[i]!r}, ref={yref[i]!r}, scale={s[i]!r})")
     return worst
-
-
-def fsum_rows(A) -> np.ndarray:
-    """Correctly rounded row sums of A (math.fsum), independent of O1."""
-    return np.array([math.fsum(A.val[A.row_ptr[i]:A.row_ptr[i + 1]]) for i in range(A.n_rows)])

@@ -69,7 +69,7 @@ def test_unit_vectors_give_columns(oracle_mod):
 def test_ones_give_row_sums(oracle_mod):
     A = matgen.random_small(150, 0.1, 22, empty_rows=4)
     y = oracle_mod.spmv(A, np.ones(A.n_cols))
-    ref = oracle_mod.fsum_rows(A)
+    ref = np.array([math.fsum(A.val[A.row_ptr[i]:A.row_ptr[i + 1]]) for i in range(A.n_rows)])
     s = oracle_mod.abs_scale(A, np.ones(A.n_cols))
     m = int(np.diff(A.row_ptr).max())
     assert np.all(np.abs(y - ref) <= _gamma(m) * s + 0.5 * np.spacing(np.abs(ref)))
@@ -233,6 +233,17 @@ def test_tolerance_helper_flags_errors(oracle_mod):
         oracle_mod.assert_close(y + np.array([0, 0, 1e-300]), y, s)
     with pytest.raises(AssertionError):
         oracle_mod.assert_close(np.array([np.nan, 2.0, 0.0]), y, s)
+
+
+def test_scaled_error_hand_values(oracle_mod):
+    """|y - ref| / s per row, 0 for an exact match at zero scale, inf for a
+    mismatch at zero scale or a NaN on either side."""
+    y = np.array([1.5, -2.0, 0.0, 0.0, 7.0, np.nan])
+    ref = np.array([1.0, -2.0, 0.0, 1e-300, 7.0, 1.0])
+    s = np.array([4.0, 0.5, 0.0, 0.0, 2.0, 1.0])
+    e = oracle_mod.scaled_error(y, ref, s)
+    assert e[0] == 0.125 and e[1] == 0.0 and e[2] == 0.0 and e[4] == 0.0
+    assert np.isinf(e[3]) and np.isinf(e[5])
 
 
 def test_gamma_matches_fsum_bound(oracle_mod):
