@@ -62,12 +62,12 @@ def time_launches(torch, fn, steps, warmup):
 
 
 def time_cold(torch, fn, flush, reps):
-    """Median per-launch time with L2 and the 256 MB Infinity Cache flushed
-    first by reading (not writing) a larger buffer, so no dirty lines are left
-    to be written back during the timed launch."""
+    """Median time of single launches, each after a cache flush (`flush`
+    reads 1 GiB with cache-allocating loads, evicting L2 and the 256 MB
+    Infinity Cache and leaving no dirty lines), bracketed by HIP events."""
     ts = []
-    for i in range(reps):
-        flush.sum()
+    for _ in range(reps):
+        flush()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         fn()
@@ -75,6 +75,141 @@ def time_cold(torch, fn, flush, reps):
         torch.cuda.synchronize()
         ts.append(ev0.elapsed_time(ev1) * 1e-3)
     return statistics.median(ts)
+
+
+def time_cold_graph(torch, fn, flush, n=20, reps=7):
+    """What a product adds to a stream after a cache flush: a HIP graph of n
+    (flush, product) pairs against one of n flushes, median of `reps` replays
+    each, difference per product.  `fn` and `flush` take the capture stream."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        flush(s)
+        fn(s)
+    torch.cuda.synchronize()
+    graphs = []
+    for with_product in (True, False):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(n):
+                flush(s)
+                if with_product:
+                    fn(s)
+        graphs.append(g)
+    out = []
+    for g in graphs:
+        ts = []
+        for _ in range(reps):
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            g.replay()
+            ev1.record()
+            torch.cuda.synchronize()
+            ts.append(ev0.elapsed_time(ev1) * 1e-3)
+        out.append(statistics.median(ts))
+    del graphs
+    return (out[0] - out[1]) / n
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_oracle_baseline(oracle, A, x, flops, what):
+    """The CPU oracle (plain FP64 CSR, OpenMP over rows) on the whole matrix:
+    one warm-up product, then the median of 5, on 1 thread and on all the
+    threads OpenMP is given."""
+    nthr = oracle.max_threads()
+    legs = {}
+    for th in sorted({1, nthr}):
+        oracle.spmv(A, x, threads=th)
+        ts = []
+        for _ in range(5):
+            t0 = time.perf_counter()
+            oracle.spmv(A, x, threads=th)
+            ts.append(time.perf_counter() - t0)
+        legs[th] = statistics.median(ts)
+    return {"value": round(flops / legs[nthr] / 1e9, 3), "unit": "GFLOP/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{what}: one warm-up product, then the median of 5, on {nthr} threads "
+                      f"(and on 1: single_thread_GFLOPs)",
+            "single_thread_GFLOPs": round(flops / legs[1] / 1e9, 3),
+            "ms_per_product": {str(k): round(v * 1e3, 3) for k, v in legs.items()},
+            "cpu_model": cpu_model()}
+
+
+class RocsparseSpmv:
+    """The vendor CSR product as a comparator: rocSPARSE's generic SpMV
+    (the copy bundled with torch, so that it shares torch's HIP runtime),
+    FP64, int32 indices, one algorithm (adaptive by default), its buffer
+    sizing and preprocessing done once, so that a call is the compute stage
+    alone, on torch's current stream."""
+    ALG = {"adaptive": 2, "rowsplit": 3, "lrb": 7, "nnzsplit": 8}
+
+    def __init__(self, torch, row_ptr, col, val, x, y, alg="adaptive"):
+        import ctypes
+        self.ct = ctypes
+        self.lib = ctypes.CDLL(os.path.join(os.path.dirname(torch.__file__), "lib", "librocsparse.so"))
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        n = len(row_ptr) - 1
+        dev = x.device
+        self.keep = [torch.from_numpy(row_ptr.astype("int32")).to(dev), torch.from_numpy(col.astype("int32")).to(dev),
+                     torch.from_numpy(val).to(dev), x, y]
+        rp, ci, v = self.keep[:3]
+        self.h, self.A, self.X, self.Y = vp(), vp(), vp(), vp()
+        self._ok(self.lib.rocsparse_create_handle(ctypes.byref(self.h)), "create_handle")
+        self._ok(self.lib.rocsparse_set_stream(self.h, vp(torch.cuda.current_stream().cuda_stream)), "set_stream")
+        self._ok(self.lib.rocsparse_create_csr_descr(ctypes.byref(self.A), i64(n), i64(n), i64(len(col)),
+                                                     vp(rp.data_ptr()), vp(ci.data_ptr()), vp(v.data_ptr()),
+                                                     2, 2, 0, 152), "create_csr_descr")
+        self._ok(self.lib.rocsparse_create_dnvec_descr(ctypes.byref(self.X), i64(n), vp(x.data_ptr()), 152), "dnvec x")
+        self._ok(self.lib.rocsparse_create_dnvec_descr(ctypes.byref(self.Y), i64(n), vp(y.data_ptr()), 152), "dnvec y")
+        self.alpha, self.beta = ctypes.c_double(1.0), ctypes.c_double(0.0)
+        self.alg = self.ALG[alg]
+        size = ctypes.c_size_t(0)
+        self._stage(1, size, None)
+        self.buf = torch.empty(max(int(size.value), 256), dtype=torch.uint8, device=dev)
+        self._stage(2, size, self.buf)
+        torch.cuda.synchronize()
+        self.size = size
+
+    def _ok(self, st, what):
+        if st != 0:
+            raise RuntimeError(f"rocsparse {what}: status {st}")
+
+    def _stage(self, stage, size, buf):
+        ct = self.ct
+        self._ok(self.lib.rocsparse_spmv(self.h, 111, ct.byref(self.alpha), self.A, self.X, ct.byref(self.beta),
+                                         self.Y, 152, self.alg, stage, ct.byref(size),
+                                         ct.c_void_p(buf.data_ptr() if buf is not None else 0)), f"spmv stage {stage}")
+
+    def __call__(self):
+        self._stage(3, self.size, self.buf)
+
+    def close(self):
+        for f, o in (("rocsparse_destroy_dnvec_descr", self.X), ("rocsparse_destroy_dnvec_descr", self.Y),
+                     ("rocsparse_destroy_spmat_descr", self.A), ("rocsparse_destroy_handle", self.h)):
+            getattr(self.lib, f)(o)
+
+
+def rocsparse_time(torch, row_ptr, col, val, x, steps, warmup):
+    """rocSPARSE (adaptive CSR) per product: wall-clock and HIP-event time,
+    and its result; None and the error if the library cannot be used."""
+    y = torch.empty_like(x)
+    try:
+        op = RocsparseSpmv(torch, row_ptr, col, val, x, y)
+    except (OSError, AttributeError, RuntimeError) as e:
+        return None, None, None, str(e)
+    wall, kern = time_launches(torch, op, steps, warmup)
+    torch.cuda.synchronize()
+    op.close()
+    return wall, kern, y, None
 
 
 def fp64_products(row_ptr, col, val, X):
@@ -136,7 +271,8 @@ def main():
     import torch
 
     import matgen
-    from paper_2204_06666_amd import EHYB_LOAD_AUTO, EHYB_LOAD_STREAM, Plan, csr_spmv, device_info, probe_read
+    from paper_2204_06666_amd import (EHYB_LOAD_AUTO, EHYB_LOAD_CACHED, EHYB_LOAD_STREAM, Plan, cache_flush, csr_spmv,
+                                      device_info, probe_read)
     from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS, PAPER_SPLIT_PARAMS
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -220,7 +356,7 @@ def main():
     ci = torch.from_numpy(A.col).to(dev)
     cv = torch.from_numpy(A.val).to(dev)
     csr = {}
-    for lanes in (4, 8, 16, 32):
+    for lanes in (2, 4, 8, 16, 32):
         w, k = time_launches(torch, lambda: csr_spmv(rp, ci, cv, xo, yo, lanes), args.steps,
                              args.warmup)
         csr[lanes] = (w, k)
@@ -235,10 +371,16 @@ def main():
     ci2 = torch.from_numpy(dci).to(dev)
     cv2 = torch.from_numpy(dval).to(dev)
     csr_re = {}
-    for lanes in (8, 16, 32):
+    for lanes in (2, 4, 8, 16):
         csr_re[lanes] = time_launches(torch, lambda: csr_spmv(rp2, ci2, cv2, xp, yo, lanes),
                                       args.steps, args.warmup)
     best_re = min(csr_re, key=lambda k: csr_re[k][0])
+
+    # --- the vendor CSR product (rocSPARSE, through torch's sparse CSR), as context
+    log("timing rocSPARSE (torch sparse CSR) on the matrix as given and on P A P^T")
+    rs_wall, rs_kern, y_rs, rs_err = rocsparse_time(torch, A.row_ptr, A.col, A.val, xo, args.steps, args.warmup)
+    rs2_wall, rs2_kern, _, _ = rocsparse_time(torch, drp, dci, dval, xp, args.steps, args.warmup)
+    del drp, dci, dval, rp2, ci2, cv2
 
     # --- HBM bandwidth probe (read stream over 4 GiB, best of 10)
     log("bandwidth probe")
@@ -252,34 +394,42 @@ def main():
     hbm_meas = max(bw)
     del buf
 
-    # --- cold runs: flush L2 and the 256 MB Infinity Cache before each launch
+    # --- cold runs: L2 and the 256 MB Infinity Cache flushed before each launch
     log("cold timing")
-    flush = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
-    cold_ehyb = time_cold(torch, lambda: plan.spmv(xp, yp), flush, 30)
-    # a cold product reuses nothing from the caches: streaming loads suit it
-    plan.set_load_mode(EHYB_LOAD_STREAM)
-    cold_stream = time_cold(torch, lambda: plan.spmv(xp, yp), flush, 30)
+    fbuf = torch.ones(1 << 30, dtype=torch.uint8, device=dev)
+    flush = lambda st=None: cache_flush(fbuf, sink, stream=st)  # noqa: E731
+    cold = {}
+    for mode_name, mode in (("plain", EHYB_LOAD_CACHED), ("stream", EHYB_LOAD_STREAM)):
+        plan.set_load_mode(mode)
+        cold[mode_name] = {
+            "single_launch_us": time_cold(torch, lambda: plan.spmv(xp, yp), flush, 30),
+            "after_flush_in_graph_us": time_cold_graph(torch, lambda st: plan.spmv(xp, yp, stream=st), flush)}
     plan.set_load_mode(EHYB_LOAD_AUTO)
     cold_csr = time_cold(torch, lambda: csr_spmv(rp, ci, cv, xo, yo, best_l), flush, 30)
-    del flush
+    del fbuf
+    # the cold headline: streaming loads (a product that reuses nothing from the
+    # caches), the incremental time in a stream after other work
+    cold_s = cold["stream"]["after_flush_in_graph_us"]
+    log(f"cold: {json.dumps(cold)}")
 
-    # --- CPU oracle baseline (bounded sample: whole matrix, repeated ~cpu-seconds)
+    # --- CPU oracle baseline (the whole matrix; about a second of CPU work)
     cpu = None
     if not args.no_cpu:
         import oracle
         log("CPU oracle baseline")
-        oracle.spmv(A, x)
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            oracle.spmv(A, x)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el >= args.cpu_seconds:
-                break
-        cpu = {"value": round(flops * reps / el / 1e9, 3), "unit": "GFLOP/s",
-               "cores": oracle.max_threads(), "kind": "oracle",
-               "sample": f"whole headline matrix, {reps} products in {el:.1f} s "
-                         f"(plain FP64 CSR, OpenMP over rows)"}
+        cpu = cpu_oracle_baseline(oracle, A, x, flops, "the whole headline matrix")
+
+    # the vendor product's result against the plain CSR kernel's (both FP64)
+    rocsparse = {"what": "rocSPARSE generic SpMV, CSR adaptive algorithm, FP64, int32 indices; buffer sizing "
+                         "and preprocessing once, compute stage timed", "error": rs_err}
+    if rs_err is None:
+        y_csr = torch.empty_like(xo)
+        csr_spmv(rp, ci, cv, xo, y_csr, best_l)
+        rocsparse.update({"us_per_step": round(rs_wall * 1e6, 2), "GFLOPs": round(flops / rs_wall / 1e9, 2),
+                          "algorithmic_GBps": round(csr_bytes / rs_kern / 1e9, 1),
+                          "on_reordered_us_per_step": round(rs2_wall * 1e6, 2),
+                          "on_reordered_GFLOPs": round(flops / rs2_wall / 1e9, 2),
+                          "max_abs_diff_vs_csr_kernel": float(torch.max(torch.abs(y_rs - y_csr)).item())})
 
     kh = kernel_source_hash()
     traffic = load_traffic(kh)
@@ -305,17 +455,31 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBPS, 4),
                      "traffic": traffic, "kernel": "ehyb_spmv_kernel<EHYB_F64, L=1, plain loads>",
-                     "algorithmic_bytes_per_launch": algo, "launch_us": round(kern * 1e6, 2)},
+                     "algorithmic_bytes_per_launch": algo, "launch_us": round(kern * 1e6, 2),
+                     "timing": "warm: back-to-back launches, HIP events",
+                     "cold": {"us": round(cold_s * 1e6, 2), "achieved": round(algo / cold_s / 1e9, 1),
+                              "frac": round(algo / cold_s / 1e9 / PEAK_HBM_GBPS, 4),
+                              "pct_of_measured_hbm": round(100 * algo / cold_s / 1e9 / hbm_meas, 2),
+                              "load_mode": "stream",
+                              "protocol": "L2 and Infinity Cache flushed (1 GiB read with cache-allocating "
+                                          "loads) before each product; HIP graph of 20 (flush, product) pairs "
+                                          "minus one of 20 flushes, median of 7 replays"}},
         "cpu_baseline": cpu,
         "hbm_probe_GBps": round(hbm_meas, 1),
         "pct_of_measured_hbm": round(100 * achieved / hbm_meas, 2),
-        "csr": {"lanes_per_row": best_l, "GFLOPs": round(flops / csr_wall / 1e9, 2),
+        "csr": {"kernel": "CSR-vector, 4 entries per lane per batch, lanes per row swept",
+                "lanes_per_row": best_l, "GFLOPs": round(flops / csr_wall / 1e9, 2),
                 "us_per_step": round(csr_wall * 1e6, 2),
                 "algorithmic_GBps": round(csr_bytes / csr_kern / 1e9, 1),
-                "all": {str(k): round(v[0] * 1e6, 2) for k, v in csr.items()}},
+                "pct_of_8TBps": round(100 * csr_bytes / csr_kern / 8e12, 2),
+                "all_us": {str(k): round(v[0] * 1e6, 2) for k, v in csr.items()}},
         "speedup_vs_csr": round(csr_wall / wall, 3),
-        "csr_on_reordered": {"lanes_per_row": best_re,
-                             "GFLOPs": round(flops / csr_re[best_re][0] / 1e9, 2)},
+        "csr_on_reordered": {"lanes_per_row": best_re, "GFLOPs": round(flops / csr_re[best_re][0] / 1e9, 2),
+                             "us_per_step": round(csr_re[best_re][0] * 1e6, 2),
+                             "algorithmic_GBps": round(csr_bytes / csr_re[best_re][1] / 1e9, 1),
+                             "pct_of_8TBps": round(100 * csr_bytes / csr_re[best_re][1] / 8e12, 2)},
+        "rocsparse_context": rocsparse,
+        "speedup_vs_rocsparse": round(rs_wall / wall, 3) if rs_err is None else None,
         "ehyb_paper_split": {"GFLOPs": round(flops / wall_ps / 1e9, 2),
                              "us_per_step": round(wall_ps * 1e6, 2),
                              "algorithmic_GBps": round(st_ps["algorithmic_bytes"] / kern_ps / 1e9, 1),
@@ -324,13 +488,11 @@ def main():
                        "protocol": "HIP graph of 50 launches, median of 7 replays"},
         "ehyb_with_permutation": {"GFLOPs": round(flops / wall_u / 1e9, 2),
                                   "us_per_step": round(wall_u * 1e6, 2)},
-        "cold": {"ehyb_us": round(cold_ehyb * 1e6, 2), "csr_us": round(cold_csr * 1e6, 2),
-                 "ehyb_GFLOPs": round(flops / cold_ehyb / 1e9, 2),
-                 "ehyb_pct_measured_hbm": round(100 * algo / cold_ehyb / 1e9 / hbm_meas, 2),
-                 "ehyb_stream_loads_us": round(cold_stream * 1e6, 2),
-                 "ehyb_stream_loads_GFLOPs": round(flops / cold_stream / 1e9, 2),
-                 "ehyb_stream_loads_pct_measured_hbm": round(100 * algo / cold_stream / 1e9 / hbm_meas, 2)},
+        "cold": {k: {kk: round(vv * 1e6, 2) for kk, vv in v.items()} for k, v in cold.items()},
+        "cold_csr_us": round(cold_csr * 1e6, 2),
         "preprocess_s": round(t_pre, 2),
+        "preprocess_breakdown_s": {k: round(st[k], 3) for k in ("t_graph_s", "t_partition_s", "t_reorder_s",
+                                                                "t_encode_s")},
         "preprocess_over_spmv": round(t_pre / wall, 0),
         "kernel_source_sha256_16": kh,
     }

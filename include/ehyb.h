@@ -29,7 +29,9 @@
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Device work is enqueued on it and the call returns without waiting,
  *     except where stated.
- *   - Vectors are contiguous, dtype as stated (x, y FP64 for FP64 plans).
+ *   - Vectors are contiguous, dtype as stated (x, y FP64 for FP64 plans),
+ *     each under 4 GiB (the kernels address them with 32-bit byte offsets;
+ *     larger ones give EHYB_EUNSUPPORTED).
  *     x and y must not overlap.  x is assumed finite: padding slots multiply
  *     +0.0 by an x element, so an Inf or NaN in x may leak into rows that do
  *     not reference it.
@@ -417,10 +419,15 @@ EHYB_API ehyb_status ehyb_plan_load(const char *path, ehyb_plan **out);
 
 EHYB_API void ehyb_plan_destroy(ehyb_plan *plan);
 
-/* Baseline: plain CSR y = A x on the device, FP64, one group of
- * `lanes_per_row` lanes (power of two in [1, 64]; 0 = chosen from the mean row
- * length) per row.  row_ptr int32 [n_rows+1], col int32 [nnz], val [nnz], x,
- * y device.  The comparator of the method (CSR lineage, Section 2.2). */
+/* Baseline: plain CSR y = A x on the device, FP64 (CSR-vector): one group of
+ * `lanes_per_row` lanes (power of two in [1, 64]; 0 = the fewest whose first
+ * batch of 4 entries per lane covers a row of mean length) per row, each lane
+ * loading 4 entries per batch before using any; a wavefront holding a row of
+ * more than 1024 entries sums its rows one at a time on all 64 lanes.
+ * row_ptr int32 [n_rows+1], col int32 [nnz], val [nnz], x, y device;
+ * n_rows and nnz below 2^29 (else EHYB_EUNSUPPORTED).  Each row's sum is a
+ * fixed function of lanes_per_row.  The comparator of the method (CSR
+ * lineage, Section 2.2). */
 EHYB_API ehyb_status ehyb_csr_spmv_f64(int64_t n_rows, int64_t nnz, const int32_t *row_ptr,
                               const int32_t *col_idx, const double *val, const double *x,
                               double *y, int32_t lanes_per_row, void *stream);
@@ -430,6 +437,13 @@ EHYB_API ehyb_status ehyb_csr_spmv_f64(int64_t n_rows, int64_t nnz, const int32_
  * 8-byte partial per workgroup to `sink` (device, >= 8 * 65536 bytes).
  * copy: copies `bytes` (multiple of 16) from src to dst. */
 EHYB_API ehyb_status ehyb_probe_read(const void *buf, size_t bytes, void *sink, void *stream);
+/* Cache flush for cold timings: reads `bytes` (multiple of 16) of `buf` with
+ * ordinary loads, which allocate in the L2 caches and the 256 MB Infinity
+ * Cache, so that a buffer larger than both (1 GiB) evicts what they held
+ * (the read probe's non-temporal loads do not).  Nothing is written but one
+ * 8-byte partial per workgroup to `sink` (as for ehyb_probe_read), so no
+ * dirty lines are left to be written back during the next kernel. */
+EHYB_API ehyb_status ehyb_cache_flush(const void *buf, size_t bytes, void *sink, void *stream);
 EHYB_API ehyb_status ehyb_probe_copy(const void *src, void *dst, size_t bytes, void *stream);
 
 typedef struct {

@@ -22,7 +22,7 @@ from ._abi import (EHYB_BF16, EHYB_BF16_ACC64, EHYB_F32, EHYB_F32_ACC64, EHYB_F6
                    EHYB_LOAD_STREAM, EHYB_VEC_PERMUTED, EhybError,
                    check, load)
 
-__all__ = ["Plan", "Batch", "csr_spmv", "probe_read", "probe_copy", "device_info", "version",
+__all__ = ["Plan", "Batch", "csr_spmv", "probe_read", "cache_flush", "probe_copy", "device_info", "version",
            "EhybError", "EHYB_F64", "EHYB_F32", "EHYB_BF16", "EHYB_F32_ACC64", "EHYB_BF16_ACC64",
            "EHYB_VEC_PERMUTED", "EHYB_LOAD_AUTO",
            "EHYB_LOAD_CACHED", "EHYB_LOAD_STREAM", "load"]
@@ -305,6 +305,12 @@ def csr_spmv(row_ptr32, col, val, x, y, lanes_per_row: int = 0, stream=None):
 def probe_read(buf, sink, stream=None):
     check(load().ehyb_probe_read(_ptr(buf), buf.numel() * buf.element_size(), _ptr(sink),
                                  _stream(stream)), "probe_read")
+
+
+def cache_flush(buf, sink, stream=None):
+    """Read ``buf`` with cache-allocating loads (evicts L2 and the Infinity Cache)."""
+    check(load().ehyb_cache_flush(_ptr(buf), buf.numel() * buf.element_size(), _ptr(sink),
+                                  _stream(stream)), "cache_flush")
 
 
 def probe_copy(src, dst, stream=None):

@@ -88,6 +88,7 @@ SIGNATURES = {
     "ehyb_plan_destroy": (None, [c_vp]),
     "ehyb_csr_spmv_f64": (c_i32, [c_i64, c_i64, c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, c_vp]),
     "ehyb_probe_read": (c_i32, [c_vp, c_size, c_vp, c_vp]),
+    "ehyb_cache_flush": (c_i32, [c_vp, c_size, c_vp, c_vp]),
     "ehyb_probe_copy": (c_i32, [c_vp, c_vp, c_size, c_vp]),
     "ehyb_device_info_get": (c_i32, [ctypes.POINTER(DeviceInfo)]),
     "ehyb_batch_create": (c_i32, [ctypes.POINTER(c_vp), c_i32, c_i32, ctypes.POINTER(c_vp)]),

@@ -4,13 +4,23 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <memory>
+#include <mutex>
+#include <string>
 #include <type_traits>
 
 #include "internal.h"
 
 using namespace ehyb;
+
+// Scalar buffer loads (s_buffer_load) of 8 and 16 bytes: LLVM intrinsics
+// without a clang builtin, declared by their intrinsic names.
+typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
+__device__ i32x2 llvm_s_buffer_load_x2(i32x4 rsrc, int32_t offset, int32_t policy) __asm("llvm.amdgcn.s.buffer.load.v2i32");
+__device__ i32x4 llvm_s_buffer_load_x4(i32x4 rsrc, int32_t offset, int32_t policy) __asm("llvm.amdgcn.s.buffer.load.v4i32");
 
 namespace {
 
@@ -89,7 +99,7 @@ struct BatchArgs {
 };
 
 constexpr int kErChunk = 16;    // residual steps whose loads are issued before any is used
-constexpr int kStageRegs = 4;   // 16-byte x-slice loads per thread kept in flight
+constexpr int kStageRegs = 4;   // x-slice rows per thread kept in flight
 constexpr int kHaloRegs = 4;    // halo gathers per thread kept in flight
 
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
@@ -214,6 +224,66 @@ __device__ __forceinline__ T reduce_lanes(T v) {
     return v;
 }
 
+// Raw buffer view of `bytes` bytes at p (stride 0, no swizzle): a load at
+// byte offset `off` reads p[off..], and one at or past `bytes` reads zeros
+// without touching memory.  x, the halo index lists and the residual columns
+// are read through such views, with 32-bit offsets; the library rejects
+// vectors of 4 GiB or more.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+constexpr int kBufferConfig = 0x00020000;  // gfx9 buffer descriptor word 3: 32-bit data format
+__device__ __forceinline__ Rsrc make_rsrc(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, kBufferConfig);
+}
+// The address is the view's base + `off` (per lane) + `soff` (the same for
+// the wavefront, kept in a scalar register).  aux = 2 sets the non-temporal
+// bit (as __builtin_nontemporal_load does).
+template <class T, bool NT = false>
+__device__ __forceinline__ T buf_load(Rsrc r, uint32_t off, uint32_t soff = 0) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    constexpr int aux = NT ? 2 : 0;
+    if constexpr (sizeof(T) == 2) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(r, off, soff, aux));
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, off, soff, aux));
+    } else if constexpr (sizeof(T) == 8) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, aux));
+    } else {
+        static_assert(sizeof(T) % 16 == 0, "buf_load: 2, 4, 8 or a multiple of 16 bytes");
+        struct W {
+            u32x4 w[sizeof(T) / 16];
+        } v;
+#pragma unroll
+        for (int k = 0; k < (int)(sizeof(T) / 16); ++k)
+            v.w[k] = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u * k, soff, aux);
+        return __builtin_bit_cast(T, v);
+    }
+}
+
+// Scalar buffer loads of the per-slice metadata, which is the same for the whole wavefront: the load goes
+// through the scalar data cache into scalar registers, and the wavefront waits
+// for it on the scalar counter alone.  A vector load of the same data is
+// waited for on the vector counter, which also counts the wavefront's y
+// stores, so every slice would wait for its own y store to complete.  The
+// view is range-checked like a vector buffer view: an offset at or past its
+// end reads zeros.
+__device__ __forceinline__ i32x4 scalar_rsrc(const void* p, uint32_t bytes) {
+    const uint64_t a = (uint64_t)(uintptr_t)p;
+    i32x4 r;
+    r.x = (int32_t)(uint32_t)a;
+    r.y = (int32_t)((uint32_t)(a >> 32) & 0xFFFFu);  // stride 0
+    r.z = (int32_t)bytes;
+    r.w = kBufferConfig;
+    return r;
+}
+__device__ __forceinline__ uint4 sload4(i32x4 rsrc, uint32_t off) {
+    const i32x4 v = llvm_s_buffer_load_x4(rsrc, (int32_t)off, 0);
+    return make_uint4((uint32_t)v.x, (uint32_t)v.y, (uint32_t)v.z, (uint32_t)v.w);
+}
+__device__ __forceinline__ uint2 sload2(i32x4 rsrc, uint32_t off) {
+    const i32x2 v = llvm_s_buffer_load_x2(rsrc, (int32_t)off, 0);
+    return make_uint2((uint32_t)v.x, (uint32_t)v.y);
+}
+
 // Metadata is the same for the whole wavefront: keep it in scalar registers.
 __device__ __forceinline__ uint4 uniform4(uint4 v) {
     return make_uint4(__builtin_amdgcn_readfirstlane(v.x), __builtin_amdgcn_readfirstlane(v.y),
@@ -241,6 +311,18 @@ __device__ __forceinline__ void wave_wait(int* ctr, int target) {
         __builtin_amdgcn_s_sleep(1);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
+
+// The loads of one round of an ELL slice: up to N full steps (KC entries per
+// lane each) and, in the slice's last round, its single-entry tail steps, all
+// issued before any is used.
+template <int DT, int N>
+struct EllRound {
+    static constexpr int kSteps = N;
+    typename Prec<DT>::VL v[N];
+    typename Prec<DT>::CL c[N];
+    typename Prec<DT>::V tv[Prec<DT>::KC - 1];
+    uint16_t tc[Prec<DT>::KC - 1];
+};
 
 // Counters of the two workgroup queues of one partition.
 struct Queues {
@@ -276,7 +358,7 @@ struct Queues {
 // fixed by the plan: results are bitwise reproducible.
 // The caller initialises nothing and must not touch LDS or `Q` until every
 // thread has returned (a barrier).
-template <int DT, int L, int NRHS, bool NT>
+template <int DT, int L, int NRHS, bool NT, bool PREFETCH = false>
 __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
                                                   const typename Prec<DT>::X* __restrict__ x,
                                                   typename Prec<DT>::X* __restrict__ y,
@@ -290,6 +372,13 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
     using XR = typename Row<X, NRHS>::type;
     constexpr int KC = P::KC;
     constexpr int kEll = NRHS >= 4 ? (P::kEll > 8 ? P::kEll / 2 : 4) : P::kEll;
+    // Steps of each wavefront's first slice loaded during the staging, whose
+    // registers are live at the same time: a whole round for FP64 products
+    // of one workgroup per partition (PREFETCH), none otherwise.  The other
+    // value types need more registers per step, and the batched kernel runs
+    // several workgroups per CU, so that one's staging overlaps another's
+    // streaming anyway.
+    constexpr int kPre = (PREFETCH && NRHS == 1 && DT == EHYB_F64) ? kEll : 0;
     // residual gathers in flight: whole rows of NRHS elements, about 16 registers' worth each way
     constexpr int kEr = NRHS == 1 ? kErChunk : (sizeof(X) * NRHS >= 32 ? 4 : 8);
     constexpr int XV = 16 / (int)sizeof(X);  // x elements per 16-byte load
@@ -304,86 +393,202 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
     const int lane = tid & (kWave - 1);
     const int nwaves = nthr >> 6;
     const int r = lane / L;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int s0 = a.slice_start[p];
+    const int ns = a.slice_start[p + 1] - s0;
+    // Wavefront w's first ELL slice is slice w when that slice has no residual
+    // rows (the leading ell_free[p] slices): its loads are issued during the
+    // staging below, so that they stream while the staging round trips and
+    // the barrier are waited for.  The ELL queue starts after those slices.
+    const int nfirst = kPre > 0 ? min(min(nwaves, a.ell_free[p]), ns) : 0;
+    const int e0 = a.er_slice_start[p];
+    const int ner = a.er_slice_start[p + 1] - e0;
     if (tid == 0) {
         Q.q_er = 0;
-        Q.q_ell = 0;
+        Q.q_ell = nfirst;
         Q.n_staged = 0;
         Q.n_er_done = 0;
     }
+    const V* ell_val = static_cast<const V*>(a.ell_val);
+    const i32x4 r_ell_meta = scalar_rsrc(a.ell_meta + s0, (uint32_t)ns * 16u);
 
-    // 1. x-slice into LDS (16-byte loads over the aligned body), then the halo
+    using Round = EllRound<DT, kEll>;
+    // Every load of a round is issued unconditionally through views of the
+    // slice's full steps and (last round only) of its tail steps: a load past
+    // a view's end reads 0 without a memory access, so no load sits under a
+    // branch (whose untaken path would leave its registers undefined and keep
+    // them live across the queue loop).
+    auto ell_issue = [&](const uint4& mu, uint32_t t0, auto& R) {
+        constexpr int N = std::remove_reference_t<decltype(R)>::kSteps;
+        const uint32_t width = mu.y & 0xFFFFu;  // entries per lane
+        const uint32_t steps = width / KC;      // steps of KC entries, then
+        const uint32_t tail = width % KC;       // single-entry steps
+        const Rsrc rv = make_rsrc(ell_val + mu.x, steps * (uint32_t)(kWave * sizeof(VL)));
+        const Rsrc rc = make_rsrc(a.ell_col + mu.x, steps * (uint32_t)(kWave * sizeof(CL)));
+        // the tail: one value and one column per lane per step, so that rows
+        // are not padded to a multiple of KC
+        const uint32_t tl = t0 + N >= steps ? tail : 0u;
+        const size_t tb = (size_t)mu.x + (size_t)steps * kWave * KC;
+        const Rsrc rtv = make_rsrc(ell_val + tb, tl * (uint32_t)(kWave * sizeof(V)));
+        const Rsrc rtc = make_rsrc(a.ell_col + tb, tl * (uint32_t)(kWave * sizeof(uint16_t)));
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            const uint32_t t = t0 + j;
+            R.v[j] = buf_load<VL, NT>(rv, lane * (uint32_t)sizeof(VL), t * (uint32_t)(kWave * sizeof(VL)));
+            R.c[j] = buf_load<CL, NT>(rc, lane * (uint32_t)sizeof(CL), t * (uint32_t)(kWave * sizeof(CL)));
+        }
+#pragma unroll
+        for (int j = 0; j < KC - 1; ++j) {
+            R.tv[j] = buf_load<V, NT>(rtv, lane * (uint32_t)sizeof(V), j * (uint32_t)(kWave * sizeof(V)));
+            R.tc[j] = buf_load<uint16_t, NT>(rtc, lane * 2u, j * (uint32_t)(kWave * 2));
+        }
+    };
+    // multiply-add one round against the LDS vector (x-slice and halo)
+    auto ell_consume = [&](const uint4& mu, uint32_t t0, const auto& R, Acc (&acc)[NRHS]) {
+        constexpr int N = std::remove_reference_t<decltype(R)>::kSteps;
+        const XR* xsr = reinterpret_cast<const XR*>(xs);
+        const uint32_t width = mu.y & 0xFFFFu;
+        const uint32_t steps = width / KC;
+        const uint32_t tail = width % KC;
+#pragma unroll
+        for (int j = 0; j < N; ++j)
+            if (t0 + j < steps) {
+                Acc val[KC];
+                uint32_t col[KC];
+                P::unpack(R.v[j], R.c[j], val, col);
+#pragma unroll
+                for (int e = 0; e < KC; ++e) {
+                    const XR xv = xsr[col[e]];
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k) acc[k] = fma(val[e], (Acc)lane_of<X, NRHS>(xv, k), acc[k]);
+                }
+            }
+        if (t0 + N >= steps && tail != 0) {
+#pragma unroll
+            for (int j = 0; j < KC - 1; ++j)
+                if (j < (int)tail) {
+                    const Acc vv = P::value(R.tv[j]);
+                    const XR xv = xsr[R.tc[j]];
+#pragma unroll
+                    for (int k = 0; k < NRHS; ++k) acc[k] = fma(vv, (Acc)lane_of<X, NRHS>(xv, k), acc[k]);
+                }
+        }
+    };
+    EllRound<DT, (kPre > 0 ? kPre : 1)> first;  // unused when kPre == 0
+    uint4 m_first = make_uint4(0, 0, 0, 0);
+
+    // 1. x-slice into LDS, then the halo
     {
-        const int cnt = sz * NRHS;
-        const X* src = x + (size_t)ps * NRHS;
-        int h = (int)(((16 - ((uintptr_t)src & 15)) & 15) / sizeof(X));  // elements before 16-byte alignment
-        h = h < cnt ? h : cnt;
-        const int nvec = (cnt - h) / XV;
-        // 16-byte global loads; LDS stores element by element (the LDS
-        // destination xs + h is only element-aligned)
-        typedef X XL __attribute__((ext_vector_type(16 / sizeof(X))));
-        const XL* src2 = reinterpret_cast<const XL*>(src + h);
         const int hs = a.halo_start[p];
         const int hn = a.halo_start[p + 1] - hs;
         XR* xsr = reinterpret_cast<XR*>(xs);
-        const XR* xr = reinterpret_cast<const XR*>(x);
-        // Issue the x-slice loads and the halo index loads together, then the
-        // halo gathers, before any LDS store: two dependent round trips to
-        // device memory for slices and halos that fit the registers.
-        XL stg[kStageRegs];
+        // Two dependent round trips to device memory for slices and halos
+        // that fit the registers: the halo index loads and the x-slice loads,
+        // then (once the indices are in) the halo gathers, before any LDS
+        // store.  Nothing here branches per lane: a load under a branch, or
+        // one the compiler sinks into the branch of its store, is waited for
+        // there, and the vector counter drains in order, so that wait would
+        // also wait for every load issued before it (the first slice's
+        // round, below).  Loads are buffer loads (32-bit offsets, no 64-bit
+        // address arithmetic) at indices clamped to the last valid element,
+        // and stores go to the same clamped indices: surplus lanes rewrite
+        // the last element with its own value.
+        const Rsrc r_xs = make_rsrc(x + (size_t)ps * NRHS, (uint32_t)sz * (uint32_t)sizeof(XR));
+        const Rsrc r_hidx = make_rsrc(a.halo_idx + hs, (uint32_t)hn * 4u);
+        const Rsrc r_x = make_rsrc(x, (uint32_t)((size_t)a.n * sizeof(XR)));
+        const uint32_t sz_last = (uint32_t)max(sz - 1, 0);
+        const uint32_t hn_last = (uint32_t)max(hn - 1, 0);
+        // Without a halo the gathers re-read the slice's last element and
+        // store it in its own place (the LDS may end right after the slice).
+        const bool has_halo = hn > 0;
+        const uint32_t own_last = (uint32_t)ps + sz_last;
+        uint32_t hi[kHaloRegs];
 #pragma unroll
-        for (int j = 0; j < kStageRegs; ++j) {
-            const int i = tid + j * nthr;
-            if (i < nvec) stg[j] = src2[i];
-        }
-        int hi[kHaloRegs];
+        for (int j = 0; j < kHaloRegs; ++j)
+            hi[j] = buf_load<uint32_t>(r_hidx, min((uint32_t)(tid + j * nthr), hn_last) * 4u);
+        XR xv[kStageRegs];
 #pragma unroll
-        for (int j = 0; j < kHaloRegs; ++j) {
-            const int i = tid + j * nthr;
-            if (i < hn) hi[j] = a.halo_idx[hs + i];
-        }
+        for (int j = 0; j < kStageRegs; ++j)
+            xv[j] = buf_load<XR>(r_xs, min((uint32_t)(tid + j * nthr), sz_last) * (uint32_t)sizeof(XR));
         XR hv[kHaloRegs];
 #pragma unroll
-        for (int j = 0; j < kHaloRegs; ++j) {
-            const int i = tid + j * nthr;
-            if (i < hn) hv[j] = xr[hi[j]];
+        for (int j = 0; j < kHaloRegs; ++j) hv[j] = buf_load<XR>(r_x, (has_halo ? hi[j] : own_last) * (uint32_t)sizeof(XR));
+        // partitions or halos beyond the registers' reach (large LDS budgets):
+        // the rest, row by row, before the first slice's loads are issued
+        for (int i = tid + kStageRegs * nthr; i < sz; i += nthr)
+            xsr[i] = buf_load<XR>(r_xs, (uint32_t)i * (uint32_t)sizeof(XR));
+        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr)
+            xsr[sz + i] = buf_load<XR>(r_x, buf_load<uint32_t>(r_hidx, (uint32_t)i * 4u) * (uint32_t)sizeof(XR));
+        // The first ELL slice's first round, after the gathers, so that
+        // waiting for the gathers does not wait for it.  Issued by every
+        // wavefront, without a branch: one without a first slice reads
+        // metadata past the view's end (zeros: a slice of width 0, whose
+        // loads read nothing from memory).
+        if constexpr (kPre > 0) {
+            m_first = sload4(r_ell_meta, wave < nfirst ? (uint32_t)wave * 16u : 0xFFFFFFF0u);
+            ell_issue(m_first, 0, first);
         }
 #pragma unroll
-        for (int j = 0; j < kStageRegs; ++j) {
-            const int i = tid + j * nthr;
-            if (i < nvec) {
+        for (int j = 0; j < kStageRegs; ++j) xsr[min((uint32_t)(tid + j * nthr), sz_last)] = xv[j];
 #pragma unroll
-                for (int k = 0; k < XV; ++k) xs[h + XV * i + k] = stg[j][k];
+        for (int j = 0; j < kHaloRegs; ++j)
+            xsr[has_halo ? sz + min((uint32_t)(tid + j * nthr), hn_last) : sz_last] = hv[j];
+    }
+    bool er_ready = ner == 0;
+    // the rest of a slice after its first round, the residual sums of its
+    // rows (waiting, if needed, until the residual queue is drained) and
+    // one store of y per row
+    auto ell_finish = [&](const uint4& mu, uint32_t t_done, Acc (&acc)[NRHS]) {
+        const uint32_t steps = (mu.y & 0xFFFFu) / KC;
+        for (uint32_t t0 = t_done; t0 < steps; t0 += kEll) {
+            Round R;
+            ell_issue(mu, t0, R);
+            ell_consume(mu, t0, R, acc);
+        }
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<L>(acc[k]);
+        const uint64_t mask = ((uint64_t)mu.w << 32) | mu.z;
+        if (mask != 0 && !er_ready) {
+            wave_wait(&Q.n_er_done, ner);
+            er_ready = true;
+        }
+        const int lr = (int)(mu.y >> 16) * C + r;
+        if ((lane & (L - 1)) == 0 && lr < sz) {
+            if ((mask >> r) & 1u) {
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) acc[k] += yer[(size_t)lr * NRHS + k];
+            }
+            if constexpr (NRHS == 1) {
+                y[ps + lr] = (X)acc[0];
+            } else {
+                XR out;
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) out[k] = (X)acc[k];
+                reinterpret_cast<XR*>(y)[ps + lr] = out;
             }
         }
-        for (int i = tid + kStageRegs * nthr; i < nvec; i += nthr) {
-            const XL v = src2[i];
-#pragma unroll
-            for (int k = 0; k < XV; ++k) xs[h + XV * i + k] = v[k];
-        }
-        if (tid < h) xs[tid] = src[tid];
-        const int tail = h + XV * nvec;
-        if (tid < cnt - tail) xs[tail + tid] = src[tail + tid];
-        // halo after the x-slice
-#pragma unroll
-        for (int j = 0; j < kHaloRegs; ++j) {
-            const int i = tid + j * nthr;
-            if (i < hn) xsr[sz + i] = hv[j];
-        }
-        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr) xsr[sz + i] = xr[a.halo_idx[hs + i]];
-    }
+    };
     __syncthreads();  // counters initialised, x-slice and halo in LDS
 
+    // the prefetched first slice (it has no residual rows: nothing to wait for)
+    if (wave < nfirst) {
+        Acc acc[NRHS];
+#pragma unroll
+        for (int k = 0; k < NRHS; ++k) acc[k] = 0;
+        ell_consume(m_first, 0, first, acc);
+        ell_finish(m_first, kPre, acc);
+    }
+
     // 2. residual queue
-    const int e0 = a.er_slice_start[p];
-    const int ner = a.er_slice_start[p + 1] - e0;
     {
         const V* er_val = static_cast<const V*>(a.er_val);
         const XR* xr = reinterpret_cast<const XR*>(x);
+        const i32x4 r_meta = scalar_rsrc(a.er_meta + e0, (uint32_t)ner * 8u);
         int it = wave_fetch_add(&Q.q_er, lane);
-        uint2 m = it < ner ? a.er_meta[e0 + it] : make_uint2(0, 0);
+        uint2 m = sload2(r_meta, (uint32_t)it * 8u);
         while (it < ner) {
             const int itn = wave_fetch_add(&Q.q_er, lane);
-            const uint2 mn = itn < ner ? a.er_meta[e0 + itn] : make_uint2(0, 0);
+            const uint2 mn = sload2(r_meta, (uint32_t)itn * 8u);
             const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
             const uint32_t my = __builtin_amdgcn_readfirstlane(m.y);
             const uint32_t steps = my & ~kErWide;
@@ -448,94 +653,20 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
     }
 
     // 3. ELL queue
-    const V* ell_val = static_cast<const V*>(a.ell_val);
-    const XR* xsr = reinterpret_cast<const XR*>(xs);
-    const int s0 = a.slice_start[p];
-    const int ns = a.slice_start[p + 1] - s0;
-    bool er_ready = ner == 0;
     int item = wave_fetch_add(&Q.q_ell, lane);
-    uint4 m = item < ns ? a.ell_meta[s0 + item] : make_uint4(0, 0, 0, 0);
+    uint4 m = sload4(r_ell_meta, (uint32_t)item * 16u);
     while (item < ns) {
         const int nxt = wave_fetch_add(&Q.q_ell, lane);
         // the next slice's metadata travels while this slice streams
-        const uint4 mn = nxt < ns ? a.ell_meta[s0 + nxt] : make_uint4(0, 0, 0, 0);
+        const uint4 mn = sload4(r_ell_meta, (uint32_t)nxt * 16u);
         const uint4 mu = uniform4(m);
-        const uint32_t width = mu.y & 0xFFFFu;  // entries per lane
-        const uint32_t steps = width / KC;      // steps of KC entries, then
-        const uint32_t tail = width % KC;       // single-entry steps
-        const int j0 = (int)(mu.y >> 16);
-        const VL* v2 = reinterpret_cast<const VL*>(ell_val + mu.x) + lane;
-        const CL* c2 = reinterpret_cast<const CL*>(a.ell_col + mu.x) + lane;
         Acc acc[NRHS];
 #pragma unroll
         for (int k = 0; k < NRHS; ++k) acc[k] = 0;
-        for (uint32_t t0 = 0; t0 < steps; t0 += kEll) {
-            VL v[kEll];
-            CL c[kEll];
-#pragma unroll
-            for (int j = 0; j < kEll; ++j)
-                if (t0 + j < steps) {
-                    v[j] = ld<NT>(v2 + (size_t)(t0 + j) * kWave);
-                    c[j] = ld<NT>(c2 + (size_t)(t0 + j) * kWave);
-                }
-#pragma unroll
-            for (int j = 0; j < kEll; ++j)
-                if (t0 + j < steps) {
-                    Acc val[KC];
-                    uint32_t col[KC];
-                    P::unpack(v[j], c[j], val, col);
-#pragma unroll
-                    for (int e = 0; e < KC; ++e) {
-                        const XR xv = xsr[col[e]];
-#pragma unroll
-                        for (int k = 0; k < NRHS; ++k)
-                            acc[k] = fma(val[e], (Acc)lane_of<X, NRHS>(xv, k), acc[k]);
-                    }
-                }
-        }
-        if (tail != 0) {
-            // the slice's last entries: one value and one column per lane per
-            // step, so that rows are not padded to a multiple of KC
-            const size_t tb = (size_t)mu.x + (size_t)steps * kWave * KC + lane;
-            V tv[KC - 1];
-            uint16_t tc[KC - 1];
-#pragma unroll
-            for (int j = 0; j < KC - 1; ++j)
-                if (j < (int)tail) {
-                    tv[j] = ld<NT>(ell_val + tb + (size_t)j * kWave);
-                    tc[j] = ld<NT>(a.ell_col + tb + (size_t)j * kWave);
-                }
-#pragma unroll
-            for (int j = 0; j < KC - 1; ++j)
-                if (j < (int)tail) {
-                    const Acc vv = P::value(tv[j]);
-                    const XR xv = xsr[tc[j]];
-#pragma unroll
-                    for (int k = 0; k < NRHS; ++k) acc[k] = fma(vv, (Acc)lane_of<X, NRHS>(xv, k), acc[k]);
-                }
-        }
-#pragma unroll
-        for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<L>(acc[k]);
-        const uint64_t mask = ((uint64_t)mu.w << 32) | mu.z;
-        if (mask != 0 && !er_ready) {
-            wave_wait(&Q.n_er_done, ner);
-            er_ready = true;
-        }
-        const int lr = j0 * C + r;
-        if ((lane & (L - 1)) == 0 && lr < sz) {
-            if ((mask >> r) & 1u) {
-#pragma unroll
-                for (int k = 0; k < NRHS; ++k) acc[k] += yer[(size_t)lr * NRHS + k];
-            }
-            if constexpr (NRHS == 1) {
-                y[ps + lr] = (X)acc[0];
-            } else {
-                XR out;
-#pragma unroll
-                for (int k = 0; k < NRHS; ++k) out[k] = (X)acc[k];
-                reinterpret_cast<XR*>(y)[ps + lr] = out;
-            }
-        }
+        Round R;
+        ell_issue(mu, 0, R);
+        ell_consume(mu, 0, R, acc);
+        ell_finish(mu, kEll, acc);
         item = nxt;
         m = mn;
     }
@@ -548,7 +679,7 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     __shared__ Queues Q;
     const int p = xcd_logical_id(blockIdx.x, gridDim.x);
-    process_partition<DT, L, 1, NT>(a.m, p, static_cast<const X*>(a.x), static_cast<X*>(a.y), lds_raw, Q);
+    process_partition<DT, L, 1, NT, true>(a.m, p, static_cast<const X*>(a.x), static_cast<X*>(a.y), lds_raw, Q);
 }
 
 // Y_i = A_i X_i for a batch: persistent workgroups take (matrix, partition)
@@ -649,10 +780,41 @@ void launch_pieces(const ehyb_plan& P, bool nt, const void* x, hipStream_t s) {
                            pc, P.n_pieces, x, part);
 }
 
-// Plain CSR SpMV: L lanes per row (rows of a wavefront are consecutive),
-// strided loop over the row's entries, reduction over the L lanes.
+// Plain CSR SpMV, the comparator (CSR-vector): L lanes per row, rows of a
+// wavefront consecutive.  Each lane takes kCsrU entries per batch, L apart,
+// and issues all their column, value and x loads before using any (through
+// range-checked buffer views, so that no load sits under a branch); lanes
+// past the row's end gather x[0] and add nothing.  A wavefront that holds a
+// row longer than kCsrLong entries instead sums its rows one at a time on
+// all 64 lanes, so that a hub row is not left to L lanes.  The sum of a row
+// is a fixed function of L: results are reproducible.
+constexpr int kCsrU = 4;
+constexpr int kCsrLong = 1024;
+
+__device__ __forceinline__ double csr_batch_sum(Rsrc rc, Rsrc rv, Rsrc rx, int32_t b, int32_t len, int32_t t,
+                                                int sub, int stride, double acc) {
+    int32_t c[kCsrU];
+    double v[kCsrU];
+    double xg[kCsrU];
+#pragma unroll
+    for (int k = 0; k < kCsrU; ++k) {
+        const uint32_t q = (uint32_t)(b + t + sub + stride * k);
+        c[k] = buf_load<int32_t>(rc, q * 4u);
+        v[k] = buf_load<double>(rv, q * 8u);
+    }
+#pragma unroll
+    for (int k = 0; k < kCsrU; ++k) {
+        const bool in = t + sub + stride * k < len;
+        xg[k] = buf_load<double>(rx, in ? (uint32_t)c[k] * 8u : 0u);
+    }
+#pragma unroll
+    for (int k = 0; k < kCsrU; ++k)
+        if (t + sub + stride * k < len) acc = fma(v[k], xg[k], acc);
+    return acc;
+}
+
 template <int L>
-__global__ void __launch_bounds__(256) csr_spmv_f64_kernel(int64_t n, const int32_t* __restrict__ rp,
+__global__ void __launch_bounds__(256) csr_spmv_f64_kernel(int64_t n, int64_t nnz, const int32_t* __restrict__ rp,
                                                            const int32_t* __restrict__ ci,
                                                            const double* __restrict__ v,
                                                            const double* __restrict__ x,
@@ -660,16 +822,42 @@ __global__ void __launch_bounds__(256) csr_spmv_f64_kernel(int64_t n, const int3
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t row = gid / L;
     const int sub = (int)(gid & (L - 1));
-    double acc = 0.0;
+    const int lane = (int)(threadIdx.x & (kWave - 1));
+    const Rsrc rc = make_rsrc(ci, (uint32_t)(nnz * 4));
+    const Rsrc rv = make_rsrc(v, (uint32_t)(nnz * 8));
+    const Rsrc rx = make_rsrc(x, (uint32_t)(n * 8));
+    int32_t b = 0, len = 0;
     if (row < n) {
-        const int32_t b = rp[row], e = rp[row + 1];
-        for (int32_t q = b + sub; q < e; q += L) acc = fma(v[q], x[ci[q]], acc);
+        b = rp[row];
+        len = rp[row + 1] - b;
     }
-    if constexpr (L > 1) {
+    int mx = len;  // the wavefront's longest row
 #pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, kWave));
+    mx = __builtin_amdgcn_readfirstlane(mx);
+    if (mx <= kCsrLong) {
+        double acc = 0.0;
+        for (int32_t t = 0; t < mx; t += L * kCsrU) acc = csr_batch_sum(rc, rv, rx, b, len, t, sub, L, acc);
+        if constexpr (L > 1) {
+#pragma unroll
+            for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        }
+        if (sub == 0 && row < n) y[row] = acc;
+        return;
     }
-    if (sub == 0 && row < n) y[row] = acc;
+    // one row at a time on the whole wavefront
+    const int64_t row0 = (gid - lane) / L;
+    for (int r = 0; r < kWave / L; ++r) {
+        const int64_t rr = row0 + r;
+        if (rr >= n) break;
+        const int32_t br = __builtin_amdgcn_readfirstlane(rp[rr]);
+        const int32_t lr = __builtin_amdgcn_readfirstlane(rp[rr + 1]) - br;
+        double acc = 0.0;
+        for (int32_t t = 0; t < lr; t += kWave * kCsrU) acc = csr_batch_sum(rc, rv, rx, br, lr, t, lane, kWave, acc);
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        if (lane == 0) y[rr] = acc;
+    }
 }
 
 // Read-stream probe: every byte of buf is loaded once with 16-byte
@@ -679,21 +867,25 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // Four independent 16-byte non-temporal loads per thread in flight, 512
 // threads per workgroup: the best of the read-stream shapes measured on
 // gfx950 (about 7.1 TB/s over a 2 GiB buffer).
+// NT = false: ordinary loads, which allocate in L2 and the Infinity Cache;
+// reading a buffer larger than both this way evicts what they held (the
+// cache flush of cold timings).  Non-temporal loads do not displace it.
+template <bool NT>
 __global__ void __launch_bounds__(512) probe_read_kernel(const u32x4* __restrict__ buf, size_t n16,
                                                          uint64_t* __restrict__ sink) {
     uint32_t acc = 0;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (; i + 3 * stride < n16; i += 4 * stride) {
-        const u32x4 v0 = __builtin_nontemporal_load(buf + i);
-        const u32x4 v1 = __builtin_nontemporal_load(buf + i + stride);
-        const u32x4 v2 = __builtin_nontemporal_load(buf + i + 2 * stride);
-        const u32x4 v3 = __builtin_nontemporal_load(buf + i + 3 * stride);
+        const u32x4 v0 = ld<NT>(buf + i);
+        const u32x4 v1 = ld<NT>(buf + i + stride);
+        const u32x4 v2 = ld<NT>(buf + i + 2 * stride);
+        const u32x4 v3 = ld<NT>(buf + i + 3 * stride);
         acc ^= (v0.x ^ v0.y ^ v0.z ^ v0.w) ^ (v1.x ^ v1.y ^ v1.z ^ v1.w) ^ (v2.x ^ v2.y ^ v2.z ^ v2.w) ^
                (v3.x ^ v3.y ^ v3.z ^ v3.w);
     }
     for (; i < n16; i += stride) {
-        const u32x4 v = __builtin_nontemporal_load(buf + i);
+        const u32x4 v = ld<NT>(buf + i);
         acc ^= v.x ^ v.y ^ v.z ^ v.w;
     }
     // wave-level combine, then one store per workgroup
@@ -744,77 +936,100 @@ int launch_waves(const ehyb_plan& P) {
     return 16;
 }
 
+// Allow a kernel the full 160 KiB of gfx950 LDS as dynamic shared memory
+// (HIP's default limit is 64 KiB), once per kernel and device.  Thread-safe;
+// a failure is reported (EHYB_EDEVICE with HIP's message) and retried on the
+// next launch.
 template <class K>
-void raise_lds_limit(K* kernel, size_t lds, bool& raised) {
-    if (!raised && lds > 64 * 1024) {
-        // allow the full 160 KiB of gfx950 LDS as dynamic shared memory
-        if (hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                160 * 1024 - kStaticLds) != hipSuccess)
-            (void)hipGetLastError();
-        raised = true;
+ehyb_status raise_lds_limit(K* kernel, size_t lds) {
+    if (lds <= 64 * 1024) return EHYB_OK;
+    static std::atomic<uint64_t> done{0};  // one bit per device
+    static std::mutex mu;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(EHYB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= 64) return fail(EHYB_EUNSUPPORTED, "device index above 63");
+    const uint64_t bit = 1ull << dev;
+    if (done.load(std::memory_order_acquire) & bit) return EHYB_OK;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.load(std::memory_order_relaxed) & bit) return EHYB_OK;
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024 - kStaticLds);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(EHYB_EDEVICE, std::string("raising the kernel's LDS limit to 160 KiB: ") + hipGetErrorString(e));
     }
+    done.fetch_or(bit, std::memory_order_release);
+    return EHYB_OK;
 }
 
+// The launchers return false when no kernel is instantiated for the
+// requested shape, else true with the launch's status in `st`.
 template <int DT, int L, bool NT>
-void launch_spmv(const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
-    static bool raised = false;
-    raise_lds_limit(&ehyb_spmv_kernel<DT, L, NT>, lds, raised);
+ehyb_status launch_spmv(const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+    const ehyb_status st = raise_lds_limit(&ehyb_spmv_kernel<DT, L, NT>, lds);
+    if (st != EHYB_OK) return st;
     hipLaunchKernelGGL((ehyb_spmv_kernel<DT, L, NT>), dim3(nblocks), dim3(threads), lds, s, a);
+    return EHYB_OK;
 }
 
 template <int DT, bool NT>
-bool launch_spmv_l(int L, const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+bool launch_spmv_l(int L, const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s, ehyb_status& st) {
     switch (L) {
-        case 1: launch_spmv<DT, 1, NT>(a, nblocks, threads, lds, s); return true;
-        case 2: launch_spmv<DT, 2, NT>(a, nblocks, threads, lds, s); return true;
-        case 4: launch_spmv<DT, 4, NT>(a, nblocks, threads, lds, s); return true;
-        case 8: launch_spmv<DT, 8, NT>(a, nblocks, threads, lds, s); return true;
-        case 16: launch_spmv<DT, 16, NT>(a, nblocks, threads, lds, s); return true;
-        case 32: launch_spmv<DT, 32, NT>(a, nblocks, threads, lds, s); return true;
-        case 64: launch_spmv<DT, 64, NT>(a, nblocks, threads, lds, s); return true;
+        case 1: st = launch_spmv<DT, 1, NT>(a, nblocks, threads, lds, s); return true;
+        case 2: st = launch_spmv<DT, 2, NT>(a, nblocks, threads, lds, s); return true;
+        case 4: st = launch_spmv<DT, 4, NT>(a, nblocks, threads, lds, s); return true;
+        case 8: st = launch_spmv<DT, 8, NT>(a, nblocks, threads, lds, s); return true;
+        case 16: st = launch_spmv<DT, 16, NT>(a, nblocks, threads, lds, s); return true;
+        case 32: st = launch_spmv<DT, 32, NT>(a, nblocks, threads, lds, s); return true;
+        case 64: st = launch_spmv<DT, 64, NT>(a, nblocks, threads, lds, s); return true;
         default: return false;
     }
 }
 
 template <int DT>
-bool launch_spmv_dt(int L, bool nt, const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
-    return nt ? launch_spmv_l<DT, true>(L, a, nblocks, threads, lds, s)
-              : launch_spmv_l<DT, false>(L, a, nblocks, threads, lds, s);
+bool launch_spmv_dt(int L, bool nt, const SpmvArgs& a, int nblocks, int threads, size_t lds, hipStream_t s,
+                    ehyb_status& st) {
+    return nt ? launch_spmv_l<DT, true>(L, a, nblocks, threads, lds, s, st)
+              : launch_spmv_l<DT, false>(L, a, nblocks, threads, lds, s, st);
 }
 
 template <int DT, int L, int NRHS, bool NT>
-void launch_batched(const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
-    static bool raised = false;
-    raise_lds_limit(&ehyb_spmm_batched_kernel<DT, L, NRHS, NT>, lds, raised);
+ehyb_status launch_batched(const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+    const ehyb_status st = raise_lds_limit(&ehyb_spmm_batched_kernel<DT, L, NRHS, NT>, lds);
+    if (st != EHYB_OK) return st;
     hipLaunchKernelGGL((ehyb_spmm_batched_kernel<DT, L, NRHS, NT>), dim3(nblocks), dim3(threads), lds, s, a);
+    return EHYB_OK;
 }
 
 template <int DT, int NRHS, bool NT>
-bool launch_batched_l(int L, const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+bool launch_batched_l(int L, const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s,
+                      ehyb_status& st) {
     switch (L) {
-        case 1: launch_batched<DT, 1, NRHS, NT>(a, nblocks, threads, lds, s); return true;
-        case 4: launch_batched<DT, 4, NRHS, NT>(a, nblocks, threads, lds, s); return true;
-        case 16: launch_batched<DT, 16, NRHS, NT>(a, nblocks, threads, lds, s); return true;
+        case 1: st = launch_batched<DT, 1, NRHS, NT>(a, nblocks, threads, lds, s); return true;
+        case 4: st = launch_batched<DT, 4, NRHS, NT>(a, nblocks, threads, lds, s); return true;
+        case 16: st = launch_batched<DT, 16, NRHS, NT>(a, nblocks, threads, lds, s); return true;
         default: return false;
     }
 }
 
 template <int DT, bool NT>
-bool launch_batched_r(int L, int nrhs, const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s) {
+bool launch_batched_r(int L, int nrhs, const BatchArgs& a, int nblocks, int threads, size_t lds, hipStream_t s,
+                      ehyb_status& st) {
     switch (nrhs) {
-        case 1: return launch_batched_l<DT, 1, NT>(L, a, nblocks, threads, lds, s);
-        case 2: return launch_batched_l<DT, 2, NT>(L, a, nblocks, threads, lds, s);
-        case 4: return launch_batched_l<DT, 4, NT>(L, a, nblocks, threads, lds, s);
-        case 8: return launch_batched_l<DT, 8, NT>(L, a, nblocks, threads, lds, s);
+        case 1: return launch_batched_l<DT, 1, NT>(L, a, nblocks, threads, lds, s, st);
+        case 2: return launch_batched_l<DT, 2, NT>(L, a, nblocks, threads, lds, s, st);
+        case 4: return launch_batched_l<DT, 4, NT>(L, a, nblocks, threads, lds, s, st);
+        case 8: return launch_batched_l<DT, 8, NT>(L, a, nblocks, threads, lds, s, st);
         default: return false;
     }
 }
 
 template <int DT>
 bool launch_batched_dt(int L, int nrhs, bool nt, const BatchArgs& a, int nblocks, int threads, size_t lds,
-                       hipStream_t s) {
-    return nt ? launch_batched_r<DT, true>(L, nrhs, a, nblocks, threads, lds, s)
-              : launch_batched_r<DT, false>(L, nrhs, a, nblocks, threads, lds, s);
+                       hipStream_t s, ehyb_status& st) {
+    return nt ? launch_batched_r<DT, true>(L, nrhs, a, nblocks, threads, lds, s, st)
+              : launch_batched_r<DT, false>(L, nrhs, a, nblocks, threads, lds, s, st);
 }
 
 // Streaming (non-temporal) loads of the value and column arrays pay when the
@@ -828,6 +1043,9 @@ bool use_stream_loads(int mode, int64_t bytes) {
 }
 
 bool is_aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// The kernels read x through buffer views with 32-bit byte offsets.
+constexpr size_t kMaxVectorBytes = 0xFFFFFFFFull;
 
 }  // namespace
 
@@ -937,6 +1155,7 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
     if ((const char*)x < (const char*)y + vb && (const char*)y < (const char*)x + vb)
         return fail(EHYB_EINVAL, "x and y must not overlap");
     if (P->n == 0) return EHYB_OK;
+    if (vb > kMaxVectorBytes) return fail(EHYB_EUNSUPPORTED, "x and y are limited to 4 GiB - 1 bytes");
     hipStream_t s = (hipStream_t)stream;
     const char* blob = (const char*)P->dev_blob;
     const BlobLayout& Ly = P->layout;
@@ -972,16 +1191,18 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
         a.m.er_part = blob + Ly.ypart;
     }
     bool ok = false;
+    ehyb_status st = EHYB_OK;
     switch (P->value_dtype) {
-        case EHYB_F64: ok = launch_spmv_dt<EHYB_F64>(P->L, nt, a, nblocks, threads, lds, s); break;
-        case EHYB_F32: ok = launch_spmv_dt<EHYB_F32>(P->L, nt, a, nblocks, threads, lds, s); break;
-        case EHYB_BF16: ok = launch_spmv_dt<EHYB_BF16>(P->L, nt, a, nblocks, threads, lds, s); break;
-        case EHYB_F32_ACC64: ok = launch_spmv_dt<EHYB_F32_ACC64>(P->L, nt, a, nblocks, threads, lds, s); break;
-        case EHYB_BF16_ACC64: ok = launch_spmv_dt<EHYB_BF16_ACC64>(P->L, nt, a, nblocks, threads, lds, s); break;
+        case EHYB_F64: ok = launch_spmv_dt<EHYB_F64>(P->L, nt, a, nblocks, threads, lds, s, st); break;
+        case EHYB_F32: ok = launch_spmv_dt<EHYB_F32>(P->L, nt, a, nblocks, threads, lds, s, st); break;
+        case EHYB_BF16: ok = launch_spmv_dt<EHYB_BF16>(P->L, nt, a, nblocks, threads, lds, s, st); break;
+        case EHYB_F32_ACC64: ok = launch_spmv_dt<EHYB_F32_ACC64>(P->L, nt, a, nblocks, threads, lds, s, st); break;
+        case EHYB_BF16_ACC64: ok = launch_spmv_dt<EHYB_BF16_ACC64>(P->L, nt, a, nblocks, threads, lds, s, st); break;
         default: break;
     }
     if (!ok) return fail(EHYB_EINVAL, "bad lanes per row or value type");
-    ehyb_status st = launch_status("ehyb_spmv");
+    if (st != EHYB_OK) return st;
+    st = launch_status("ehyb_spmv");
     if (st != EHYB_OK) return st;
     if (!(flags & EHYB_VEC_PERMUTED)) return ehyb_unpermute_y(P, yout, y, stream);
     return EHYB_OK;
@@ -1101,6 +1322,7 @@ ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* co
         if (!is_aligned(X[i], eb * n_rhs) || !is_aligned(Y[i], eb * n_rhs))
             return fail(EHYB_EINVAL, "batched vectors must be aligned to a whole row (n_rhs elements)");
         const size_t vb = (size_t)B->plans[i]->n * eb * n_rhs;
+        if (vb > kMaxVectorBytes) return fail(EHYB_EUNSUPPORTED, "each X and Y is limited to 4 GiB - 1 bytes");
         const char* xi = (const char*)X[i];
         const char* yi = (const char*)Y[i];
         if (xi < yi + vb && yi < xi + vb) return fail(EHYB_EINVAL, "X and Y of a matrix must not overlap");
@@ -1118,20 +1340,21 @@ ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* co
     const bool nt = use_stream_loads(B->load_mode, B->algorithmic_bytes);
     const int nblocks = std::min(a.n_items, 256 * per_cu);
     bool ok = false;
+    ehyb_status st = EHYB_OK;
     hipStream_t s = (hipStream_t)stream;
+    const size_t lds = (size_t)B->lds_bytes;
     switch (B->value_dtype) {
-        case EHYB_F64: ok = launch_batched_dt<EHYB_F64>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
-        case EHYB_F32: ok = launch_batched_dt<EHYB_F32>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
-        case EHYB_BF16: ok = launch_batched_dt<EHYB_BF16>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s); break;
-        case EHYB_F32_ACC64:
-            ok = launch_batched_dt<EHYB_F32_ACC64>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s);
-            break;
+        case EHYB_F64: ok = launch_batched_dt<EHYB_F64>(B->L, n_rhs, nt, a, nblocks, threads, lds, s, st); break;
+        case EHYB_F32: ok = launch_batched_dt<EHYB_F32>(B->L, n_rhs, nt, a, nblocks, threads, lds, s, st); break;
+        case EHYB_BF16: ok = launch_batched_dt<EHYB_BF16>(B->L, n_rhs, nt, a, nblocks, threads, lds, s, st); break;
+        case EHYB_F32_ACC64: ok = launch_batched_dt<EHYB_F32_ACC64>(B->L, n_rhs, nt, a, nblocks, threads, lds, s, st); break;
         case EHYB_BF16_ACC64:
-            ok = launch_batched_dt<EHYB_BF16_ACC64>(B->L, n_rhs, nt, a, nblocks, threads, (size_t)B->lds_bytes, s);
+            ok = launch_batched_dt<EHYB_BF16_ACC64>(B->L, n_rhs, nt, a, nblocks, threads, lds, s, st);
             break;
         default: break;
     }
     if (!ok) return fail(EHYB_EUNSUPPORTED, "no batched kernel for this value type, rows_per_wave and n_rhs");
+    if (st != EHYB_OK) return st;
     return launch_status("ehyb_spmm_batched");
 }
 
@@ -1143,11 +1366,14 @@ ehyb_status ehyb_csr_spmv_f64(int64_t n_rows, int64_t nnz, const int32_t* row_pt
     if (n_rows < 0 || nnz < 0) return fail(EHYB_EINVAL, "negative size");
     if (n_rows == 0) return EHYB_OK;
     if (!row_ptr || !x || !y || (nnz > 0 && (!col_idx || !val))) return fail(EHYB_EINVAL, "null argument");
-    if (nnz > INT32_MAX) return fail(EHYB_EUNSUPPORTED, "int32 row pointers limit nnz to 2^31-1");
+    if (nnz >= (1ll << 29) || n_rows >= (1ll << 29))
+        return fail(EHYB_EUNSUPPORTED, "the CSR kernel addresses values and x with 32-bit byte offsets (below 2^29 entries)");
     int L = lanes_per_row;
     if (L == 0) {
         const double mean = (double)nnz / (double)n_rows;
-        L = mean <= 4 ? 2 : mean <= 8 ? 4 : mean <= 16 ? 8 : mean <= 32 ? 16 : mean <= 64 ? 32 : 64;
+        // the fewest lanes whose first batch covers a row of mean length
+        L = 1;
+        while (L < 64 && L * kCsrU < mean) L *= 2;
     }
     if (L < 1 || L > 64 || (L & (L - 1))) return fail(EHYB_EINVAL, "lanes_per_row must be a power of two <= 64");
     const int64_t threads = n_rows * L;
@@ -1156,7 +1382,7 @@ ehyb_status ehyb_csr_spmv_f64(int64_t n_rows, int64_t nnz, const int32_t* row_pt
     hipStream_t s = (hipStream_t)stream;
 #define EHYB_CSR_CASE(LL)                                                                            \
     case LL:                                                                                         \
-        hipLaunchKernelGGL(csr_spmv_f64_kernel<LL>, dim3((unsigned)nb), dim3(256), 0, s, n_rows, row_ptr, \
+        hipLaunchKernelGGL(csr_spmv_f64_kernel<LL>, dim3((unsigned)nb), dim3(256), 0, s, n_rows, nnz, row_ptr, \
                            col_idx, val, x, y);                                                      \
         break;
     switch (L) {
@@ -1172,15 +1398,27 @@ ehyb_status ehyb_csr_spmv_f64(int64_t n_rows, int64_t nnz, const int32_t* row_pt
     return launch_status("csr_spmv");
 }
 
-ehyb_status ehyb_probe_read(const void* buf, size_t bytes, void* sink, void* stream) {
+static ehyb_status probe_read_launch(bool nt, const void* buf, size_t bytes, void* sink, void* stream) {
     if (!buf || !sink) return fail(EHYB_EINVAL, "null argument");
     if (bytes % 16 || !is_aligned(buf, 16)) return fail(EHYB_EINVAL, "bytes and buf must be 16-byte multiples");
     if (bytes == 0) return EHYB_OK;
     const size_t n16 = bytes / 16;
     const int nb = (int)std::min<size_t>(16384, std::max<size_t>(1, n16 / (512 * 4)));
-    hipLaunchKernelGGL(probe_read_kernel, dim3(nb), dim3(512), 0, (hipStream_t)stream, (const u32x4*)buf, n16,
-                       (uint64_t*)sink);
-    return launch_status("probe_read");
+    if (nt)
+        hipLaunchKernelGGL(probe_read_kernel<true>, dim3(nb), dim3(512), 0, (hipStream_t)stream, (const u32x4*)buf,
+                           n16, (uint64_t*)sink);
+    else
+        hipLaunchKernelGGL(probe_read_kernel<false>, dim3(nb), dim3(512), 0, (hipStream_t)stream, (const u32x4*)buf,
+                           n16, (uint64_t*)sink);
+    return launch_status(nt ? "probe_read" : "cache_flush");
+}
+
+ehyb_status ehyb_probe_read(const void* buf, size_t bytes, void* sink, void* stream) {
+    return probe_read_launch(true, buf, bytes, sink, stream);
+}
+
+ehyb_status ehyb_cache_flush(const void* buf, size_t bytes, void* sink, void* stream) {
+    return probe_read_launch(false, buf, bytes, sink, stream);
 }
 
 ehyb_status ehyb_probe_copy(const void* src, void* dst, size_t bytes, void* stream) {

@@ -5,13 +5,25 @@ Reads, from directories written by rocprofv3 (CSV output):
     the average of the EHYB dispatches inside the benchmark's timed window;
   * a --pmc FETCH_SIZE run and a --pmc WRITE_SIZE run of profile_kernels.py
     -> HBM bytes per EHYB launch, each counter scaled by what it reports for
-    a copy of a known number of bytes.
+    a copy of a known number of bytes;
+  * a --pmc run of the read-request counters by size (TCC_EA0_RDREQ_32B_sum,
+    _64B_sum, _128B_sum and TCC_EA0_RDREQ_sum) and one of the write-request
+    counters (TCC_EA0_WRREQ_sum, TCC_EA0_WRREQ_64B_sum) -> HBM bytes per
+    launch counted request by request (32, 64 or 128 bytes each), checked on
+    the copy probe, whose bytes are known;
+  * optionally a --pmc run of LDS counters (instructions, bank-conflict and
+    active cycles).
+
+The traffic quoted is the request-size count; FETCH_SIZE (which on gfx950
+reads back about half of a copy's bytes) scaled by the copy probe is printed
+beside it as a cross-check.
 
 Writes a markdown summary and a JSON file with the per-launch traffic and the
 hash of the kernel source it was measured on.
 
     python3 paper_2204_06666_amd/profile_summary.py --trace DIR --fetch DIR --write DIR \
-        --fetch-log FILE --out profiles/NAME.md --traffic profiles/NAME_traffic.json
+        --rdreq DIR --wrreq DIR [--lds DIR] --fetch-log FILE \
+        --out profiles/NAME.md --traffic profiles/NAME_traffic.json
 """
 import argparse
 import csv
@@ -48,7 +60,9 @@ def trace_summary(trace_dir, warmup, steps, kernel=KERNEL, top=10):
     return stats[:top], (statistics.mean(window) if window else None), len(ehyb)
 
 
-def pmc_values(pmc_dir, counter, kernel=KERNEL):
+def pmc_values(pmc_dir, counter, kernel=KERNEL, scale=1024.0):
+    """Mean per dispatch of `counter` for the EHYB kernel and for the copy
+    probe (FETCH_SIZE / WRITE_SIZE are KiB: scale 1024; request counts: 1)."""
     rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "**", "*counter_collection.csv")))))
     out = {}
     for r in rows:
@@ -57,8 +71,33 @@ def pmc_values(pmc_dir, counter, kernel=KERNEL):
         name = r["Kernel_Name"]
         key = "ehyb" if kernel in name else ("copy" if "probe_copy_kernel" in name else None)
         if key:
-            out.setdefault(key, []).append(float(r["Counter_Value"]) * 1024.0)  # KiB -> bytes
+            out.setdefault(key, []).append(float(r["Counter_Value"]) * scale)
     return {k: statistics.mean(v) for k, v in out.items()}
+
+
+def request_bytes(rd_dir, wr_dir, kernel):
+    """Bytes read and written per dispatch, request by request."""
+    n = {sz: pmc_values(rd_dir, f"TCC_EA0_RDREQ_{sz}B_sum", kernel, 1.0) for sz in (32, 64, 128)}
+    tot = pmc_values(rd_dir, "TCC_EA0_RDREQ_sum", kernel, 1.0)
+    wr = pmc_values(wr_dir, "TCC_EA0_WRREQ_sum", kernel, 1.0)
+    wr64 = pmc_values(wr_dir, "TCC_EA0_WRREQ_64B_sum", kernel, 1.0)
+    out = {}
+    for key in ("ehyb", "copy"):
+        reads = {sz: n[sz][key] for sz in n}
+        out[key] = {"read_requests": {str(sz): round(v) for sz, v in reads.items()},
+                    "read_requests_total": round(tot[key]),
+                    "read_bytes": sum(sz * v for sz, v in reads.items()),
+                    "write_requests": round(wr[key]), "write_requests_64B": round(wr64[key]),
+                    "write_bytes": 64.0 * wr64[key] + 32.0 * (wr[key] - wr64[key])}
+    return out
+
+
+LDS_COUNTERS = ("SQ_INSTS_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_LDS_IDX_ACTIVE", "SQ_LDS_ADDR_CONFLICT", "SQ_WAVES",
+                "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES", "SQ_WAIT_INST_LDS")
+
+
+def lds_values(lds_dir, kernel):
+    return {c: pmc_values(lds_dir, c, kernel, 1.0).get("ehyb") for c in LDS_COUNTERS}
 
 
 def main():
@@ -66,6 +105,9 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
+    ap.add_argument("--rdreq", required=True, help="--pmc run of the read-request counters by size")
+    ap.add_argument("--wrreq", required=True, help="--pmc run of the write-request counters")
+    ap.add_argument("--lds", default=None, help="--pmc run of the LDS counters")
     ap.add_argument("--fetch-log", required=True, help="stdout of profile_kernels.py")
     ap.add_argument("--bench-json", default=None, help="bench.py output of the traced run")
     ap.add_argument("--warmup", type=int, default=20)
@@ -87,9 +129,15 @@ def main():
     write = pmc_values(args.write, "WRITE_SIZE", kernel)
     f_scale = copy_r / fetch["copy"]
     w_scale = copy_w / write["copy"]
-    traffic = fetch["ehyb"] * f_scale + write["ehyb"] * w_scale
+    fs_traffic = fetch["ehyb"] * f_scale + write["ehyb"] * w_scale
+    req = request_bytes(args.rdreq, args.wrreq, kernel)
+    e, c = req["ehyb"], req["copy"]
+    traffic = e["read_bytes"] + e["write_bytes"]
+    lds = lds_values(args.lds, kernel) if args.lds else None
     kh = kernel_source_hash()
-    bench = json.load(open(args.bench_json)) if args.bench_json else None
+    bench = None
+    if args.bench_json:  # the JSON line bench.py prints (the last one in the file)
+        bench = json.loads([ln for ln in open(args.bench_json) if ln.startswith("{")][-1])
 
     lines = [f"# rocprofv3 summary: {args.title}", ""]
     if args.commands:
@@ -111,21 +159,46 @@ def main():
                      f"events in the same run ({bench['value']} GFLOP/s).")
         lines.append("The kernel's overall average above also includes every other launch of the same "
                      "kernel symbol in that run.")
-    lines += ["", "## HBM traffic per launch (--pmc FETCH_SIZE, then --pmc WRITE_SIZE)", "",
-              f"Copy probe of {copy_r} bytes: FETCH_SIZE reads {fetch['copy']:.0f} bytes "
-              f"(scale {f_scale:.4f}), WRITE_SIZE {write['copy']:.0f} bytes (scale {w_scale:.4f}).", "",
-              f"| quantity | bytes |", "|---|---|",
-              f"| FETCH_SIZE x scale | {fetch['ehyb'] * f_scale:.0f} |",
-              f"| WRITE_SIZE x scale | {write['ehyb'] * w_scale:.0f} |",
-              f"| traffic per launch | {traffic:.0f} |",
+    rq = e["read_requests"]
+    lines += ["", "## HBM traffic per launch, request by request", "",
+              "Read requests by size (TCC_EA0_RDREQ_32B/64B/128B_sum; their total TCC_EA0_RDREQ_sum) and "
+              "write requests (TCC_EA0_WRREQ_sum, of which TCC_EA0_WRREQ_64B_sum are 64 bytes, the rest 32). "
+              f"Check on the copy probe ({copy_r} bytes read, {copy_w} written): "
+              f"{c['read_bytes']:.0f} bytes read ({c['read_bytes'] / copy_r:.4f}), "
+              f"{c['write_bytes']:.0f} written ({c['write_bytes'] / copy_w:.4f}).", "",
+              "| quantity | per launch |", "|---|---|",
+              f"| read requests 32 / 64 / 128 B | {rq['32']} / {rq['64']} / {rq['128']} "
+              f"(total {e['read_requests_total']}) |",
+              f"| bytes read | {e['read_bytes']:.0f} |",
+              f"| write requests (64 B of them) | {e['write_requests']} ({e['write_requests_64B']}) |",
+              f"| bytes written | {e['write_bytes']:.0f} |",
+              f"| **traffic per launch** | **{traffic:.0f}** |",
               f"| algorithmic bytes per launch | {algo} |",
-              f"| traffic / algorithmic | {traffic / algo:.3f} |", ""]
+              f"| traffic / algorithmic | {traffic / algo:.3f} |", "",
+              "Cross-check (--pmc FETCH_SIZE, then --pmc WRITE_SIZE, each scaled by what it reads for the copy "
+              f"probe: FETCH_SIZE x {f_scale:.4f}, WRITE_SIZE x {w_scale:.4f}): {fs_traffic:.0f} bytes per launch "
+              f"({fs_traffic / algo:.3f} of the algorithmic bytes).", ""]
+    if lds:
+        bc, act = lds["SQ_LDS_BANK_CONFLICT"], lds["SQ_LDS_IDX_ACTIVE"]
+        lines += ["## LDS counters per launch (--pmc " + " ".join(LDS_COUNTERS) + ")", "",
+                  "| counter | value |", "|---|---|"]
+        lines += [f"| {k} | {v:.0f} |" for k, v in lds.items() if v is not None]
+        if bc is not None and act:
+            lines += ["", f"Bank-conflict stall cycles per LDS-active cycle: {bc / act:.3f}."]
+        lines.append("")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     open(args.out, "w").write("\n".join(lines) + "\n")
     json.dump({"kernel": kernel, "workload": args.workload_name, "kernel_source_sha256_16": kh,
-               "bytes_per_launch": round(traffic), "fetch_bytes": round(fetch["ehyb"] * f_scale),
-               "write_bytes": round(write["ehyb"] * w_scale), "fetch_scale": f_scale,
-               "write_scale": w_scale, "algorithmic_bytes": algo,
+               "bytes_per_launch": round(traffic), "read_bytes": round(e["read_bytes"]),
+               "write_bytes": round(e["write_bytes"]), "read_requests": rq,
+               "read_requests_total": e["read_requests_total"], "write_requests": e["write_requests"],
+               "write_requests_64B": e["write_requests_64B"],
+               "copy_check": {"bytes_read": copy_r, "bytes_written": copy_w,
+                              "read_bytes_counted": round(c["read_bytes"]),
+                              "write_bytes_counted": round(c["write_bytes"])},
+               "fetch_size_cross_check": {"bytes_per_launch": round(fs_traffic), "fetch_scale": f_scale,
+                                          "write_scale": w_scale},
+               "lds": lds, "algorithmic_bytes": algo,
                "timed_window_avg_us": round(window_ns / 1e3, 3)},
               open(args.traffic, "w"), indent=1)
     print(open(args.out).read())

@@ -48,3 +48,4 @@ def test_null_arguments_rejected_without_gpu():
     assert lib.ehyb_plan_upload(None, None, 0, None) == _abi.EHYB_EINVAL
     assert lib.ehyb_csr_spmv_f64(-1, 0, None, None, None, None, None, 0, None) == _abi.EHYB_EINVAL
     assert lib.ehyb_probe_read(None, 16, None, None) == _abi.EHYB_EINVAL
+    assert lib.ehyb_cache_flush(None, 16, None, None) == _abi.EHYB_EINVAL

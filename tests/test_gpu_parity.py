@@ -7,8 +7,8 @@ import pytest
 
 import matgen
 import oracle
-from paper_2204_06666_amd import (EHYB_LOAD_CACHED, EHYB_LOAD_STREAM, EhybError, Plan, _abi, csr_spmv, probe_copy,
-                                  probe_read)
+from paper_2204_06666_amd import (EHYB_LOAD_CACHED, EHYB_LOAD_STREAM, EhybError, Plan, _abi, cache_flush, csr_spmv,
+                                  probe_copy, probe_read)
 from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS, PAPER_SPLIT_PARAMS
 
 pytestmark = pytest.mark.gpu
@@ -257,6 +257,19 @@ def test_csr_baseline_parity(torch, lanes):
     _check(A, x, y.cpu().numpy(), f"csr lanes={lanes}")
 
 
+@pytest.mark.parametrize("lanes", [0, 2, 8, 32])
+def test_csr_baseline_long_rows(torch, lanes):
+    """Rows of up to 7,546 entries: wavefronts holding a row longer than 1024
+    entries sum their rows one at a time on all 64 lanes."""
+    A = matgen.powerlaw(n=20000, exponent=2.1, mean_deg=20, seed=3)
+    assert int(np.diff(A.row_ptr).max()) > 1024
+    x = matgen.uniform_vector(A.n_rows, 4)
+    rp = _dev(torch, A.row_ptr.astype(np.int32))
+    y = torch.empty(A.n_rows, dtype=torch.float64, device="cuda:0")
+    csr_spmv(rp, _dev(torch, A.col), _dev(torch, A.val), _dev(torch, x), y, lanes)
+    _check(A, x, y.cpu().numpy(), f"csr long rows lanes={lanes}")
+
+
 def test_headline_full_size(torch):
     """The benchmarked workload at full size, in the benchmark's launch
     configuration: every row against the oracle."""
@@ -295,5 +308,11 @@ def test_probes(torch):
     probe_copy(src, dst)
     sink = torch.zeros(65536, dtype=torch.int64, device="cuda:0")
     probe_read(src, sink)
+    sink2 = torch.zeros(65536, dtype=torch.int64, device="cuda:0")
+    cache_flush(src, sink2)  # the same reduction with cache-allocating loads
     torch.cuda.synchronize()
     assert torch.equal(src, dst)
+    assert torch.equal(sink, sink2)
+    # the per-workgroup partials of the 32-bit words' XOR combine to the XOR of all words
+    w = np.bitwise_xor.reduce(src.cpu().numpy().view(np.uint32))
+    assert np.bitwise_xor.reduce(sink.cpu().numpy().astype(np.uint64) & 0xFFFFFFFF) == w
