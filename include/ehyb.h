@@ -405,6 +405,19 @@ EHYB_API ehyb_status ehyb_mlp_workspace_bytes(int32_t batch, size_t *bytes);
 EHYB_API ehyb_status ehyb_mlp_grad(const float *params, int32_t batch, const float *X, const float *T,
                                    float *grad, float *loss, void *workspace, size_t workspace_bytes,
                                    void *stream);
+/* ehyb_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, bit for bit, with the
+ * workspace taken from a static device array of the library instead of the
+ * caller (256 partial-sum rows of EHYB_MLP_PARAMS + 1 floats: 6.3 MiB on each
+ * device it runs on, held until the process ends, enough for any batch; a
+ * call that would need more gives EHYB_EUNSUPPORTED).  Calls no allocating
+ * routine.  Every call on a device shares that array: calls that overlap in
+ * time on one device (other streams, other host threads) race and must not
+ * be issued; calls ordered on one stream are safe.  The array's address is
+ * looked up on the first call on each device (with that device current). */
+EHYB_API ehyb_status ehyb_mlp_grad_noalloc(const float *params, int32_t batch, const float *X, const float *T,
+                                           float *grad, float *loss, void *stream);
 /* One Adam step (Kingma and Ba) in place: m, v (device, EHYB_MLP_PARAMS,
  * zero before step 1) are the moment estimates, step >= 1 counts updates,
  * bias corrections 1/(1 - beta^step) computed on the host in FP64. */

@@ -70,6 +70,7 @@ SIGNATURES = {
     "ehyb_mlp_forward": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp]),
     "ehyb_mlp_workspace_bytes": (c_i32, [c_i32, ctypes.POINTER(ctypes.c_size_t)]),
     "ehyb_mlp_grad": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, ctypes.c_size_t, c_vp]),
+    "ehyb_mlp_grad_noalloc": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "ehyb_mlp_adam": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, c_vp]),
     "ehyb_plan_stats_get": (c_i32, [c_vp, ctypes.POINTER(PlanStats)]),

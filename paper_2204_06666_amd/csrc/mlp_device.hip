@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -204,6 +205,35 @@ __global__ void __launch_bounds__(256) mlp_adam_kernel(float* __restrict__ p, co
 
 int grad_blocks(int batch) { return std::max(1, std::min(kMaxBlocks, (batch + kWaves - 1) / kWaves)); }
 
+// The workspace of ehyb_mlp_grad_noalloc: one row of partial sums per
+// workgroup of the gradient kernel, for its largest grid (any batch), in a
+// file-scope device array that each device holds until the process ends.
+constexpr size_t kScratchFloats = (size_t)kMaxBlocks * (kParams + 1);
+__device__ __align__(256) float scratch[kScratchFloats];
+
+// Device address of `scratch` on each device, looked up once per device (the
+// array's name in host code is a host-side stand-in, not a device address).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+ehyb_status scratch_for_current_device(float** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(EHYB_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(EHYB_EUNSUPPORTED, "device index above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(EHYB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return EHYB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -233,6 +263,26 @@ ehyb_status ehyb_mlp_grad(const float* params, int32_t batch, const float* X, co
         return fail(EHYB_EINVAL, "workspace smaller than ehyb_mlp_workspace_bytes");
     hipStream_t s = (hipStream_t)stream;
     float* part = (float*)workspace;
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(nb), dim3(kThreads), 0, s, params, batch, X, T, part);
+    hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, part, nb, batch, grad,
+                       loss);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? ok() : fail(EHYB_EDEVICE, std::string("mlp grad launch: ") + hipGetErrorString(e));
+}
+
+ehyb_status ehyb_mlp_grad_noalloc(const float* params, int32_t batch, const float* X, const float* T, float* grad,
+                                  float* loss, void* stream) {
+    if (batch < 1) return fail(EHYB_EINVAL, "batch must be >= 1");
+    if (!params || !X || !T || !grad) return fail(EHYB_EINVAL, "null pointer");
+    const int nb = grad_blocks(batch);
+    if ((size_t)nb * (kParams + 1) > kScratchFloats)
+        return fail(EHYB_EUNSUPPORTED, "gradient workspace larger than the library's static scratch");
+    float* part = nullptr;
+    const ehyb_status st = scratch_for_current_device(&part);
+    if (st != EHYB_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    // every workgroup writes its whole row of partial sums before the reduction
+    // reads it: nothing in the scratch needs clearing between calls
     hipLaunchKernelGGL(mlp_grad_kernel, dim3(nb), dim3(kThreads), 0, s, params, batch, X, T, part);
     hipLaunchKernelGGL(mlp_reduce_kernel, dim3((kParams + 1 + 255) / 256), dim3(256), 0, s, part, nb, batch, grad,
                        loss);
