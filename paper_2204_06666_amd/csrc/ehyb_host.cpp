@@ -362,13 +362,15 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     // most referenced first, at most halo_cap of them (original indices here).
     std::vector<std::vector<int32_t>> halo(nparts);
     std::vector<int32_t> ell_cnt(n), er_cnt(n);
+    OmpGuard guard;
 #pragma omp parallel
     {
         std::vector<int32_t> ext;
         std::vector<std::pair<int32_t, int32_t>> cnt;   // (-count, column)
-        std::vector<char> in_halo(halo_cap > 0 ? n : 0, 0);
+        std::vector<char> in_halo;
+        guard.run([&] { in_halo.assign(halo_cap > 0 ? n : 0, 0); });
 #pragma omp for schedule(dynamic, 1)
-        for (int32_t p = 0; p < nparts; ++p) {
+        for (int32_t p = 0; p < nparts; ++p) guard.run([&] {
             auto& h = halo[p];
             if (halo_cap > 0) {
                 ext.clear();
@@ -408,8 +410,9 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
             }
             if (halo_cap > 0)
                 for (int32_t j : h) in_halo[j] = 0;
-        }
+        });
     }
+    guard.rethrow();
     // each partition's rows by non-increasing ELL count (stable in the
     // original index)
 #pragma omp parallel for schedule(dynamic, 1)
@@ -445,7 +448,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     P->er_slice_start.assign(nparts + 1, 0);
     std::vector<std::vector<uint16_t>> er_rows(nparts);
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int32_t p = 0; p < nparts; ++p) {
+    for (int32_t p = 0; p < nparts; ++p) guard.run([&] {
         auto& v = er_rows[p];
         const int32_t ps = P->part_start[p];
         for (int32_t i = ps; i < P->part_start[p + 1]; ++i)
@@ -453,7 +456,8 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
         std::stable_sort(v.begin(), v.end(), [&](uint16_t a, uint16_t b) {
             return P->row_er_len[ps + a] > P->row_er_len[ps + b];
         });
-    }
+    });
+    guard.rethrow();
     // rows longer than kWideSteps steps on their L lanes (the first ones,
     // counts are non-increasing) get a wide slice each; the rest C per slice
     std::vector<int32_t> er_nwide(nparts, 0);
@@ -496,7 +500,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     std::vector<uint64_t> er_mask(ns, 0);
     P->ell_free.assign(nparts, 0);
 #pragma omp parallel for schedule(dynamic, 4)
-    for (int32_t p = 0; p < nparts; ++p) {
+    for (int32_t p = 0; p < nparts; ++p) guard.run([&] {
         const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
         const int32_t nsp = P->slice_start[p + 1] - P->slice_start[p];
         std::vector<uint64_t> mk(nsp);
@@ -524,7 +528,8 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                     nfree += pass == 0;
                 }
         P->ell_free[p] = nfree;
-    }
+    });
+    guard.rethrow();
     P->ell_meta.assign((size_t)ns * 4, 0);
     int64_t eoff = 0;
     for (int32_t s = 0; s < ns; ++s) {
@@ -581,7 +586,7 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     {
         std::vector<std::pair<int32_t, int64_t>> ent;  // (new column, source position)
 #pragma omp for schedule(dynamic, 64)
-        for (int32_t s = 0; s < ns; ++s) {
+        for (int32_t s = 0; s < ns; ++s) guard.run([&] {
             const int32_t p = slice_part[s];
             const int32_t ps = P->part_start[p], pe = P->part_start[p + 1];
             const int32_t r0 = ps + slice_j[s] * C;
@@ -628,8 +633,9 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
                 nnz_er += k2;
                 n_er_rows += k2 > 0;
             }
-        }
+        });
     }
+    guard.rethrow();
     P->nnz_ell = nnz_ell;
     P->nnz_er = nnz_er;
     P->n_er_rows = n_er_rows;

@@ -107,8 +107,9 @@ extern "C" EHYB_API ehyb_status ehyb_features(const ehyb_csr_host* A, int32_t n_
         // column spread of each 4096-row block
         const int64_t nb = (n + kColBlock - 1) / kColBlock;
         std::vector<double> spread(nb);
+        OmpGuard guard;
 #pragma omp parallel for num_threads(nt) schedule(dynamic, 1)
-        for (int64_t rb = 0; rb < nb; ++rb) {
+        for (int64_t rb = 0; rb < nb; ++rb) guard.run([&] {
             std::vector<char> seen(nb, 0);
             int64_t cnt = 0;
             for (int64_t i = rb * kColBlock; i < std::min(n, (rb + 1) * kColBlock); ++i)
@@ -120,7 +121,8 @@ extern "C" EHYB_API ehyb_status ehyb_features(const ehyb_csr_host* A, int32_t n_
                     }
                 }
             spread[rb] = (double)cnt / (double)nb;
-        }
+        });
+        guard.rethrow();
         double sp_mean = 0, sp_max = 0;
         for (double v : spread) {
             sp_mean += v;

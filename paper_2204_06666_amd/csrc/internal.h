@@ -2,7 +2,9 @@
 // launch code (HIP).  Not part of the public ABI.
 #pragma once
 
+#include <atomic>
 #include <cstdint>
+#include <exception>
 #include <memory>
 #include <new>
 #include <string>
@@ -45,6 +47,33 @@ constexpr uint32_t kErWide = 1u << 31;
 // the whole device in pieces of at most kPieceSteps steps (one wavefront
 // each); the partition's workgroup then adds its row's pieces in order.
 constexpr int kPieceSteps = 16;
+
+// An exception must not leave an OpenMP region or task: the process would
+// terminate.  Bodies that allocate run through run(): the first exception is
+// kept (later bodies are skipped, but every thread still reaches every
+// barrier of the region), and rethrow() raises it after the region, where
+// the entry point turns std::bad_alloc into EHYB_ENOMEM.
+class OmpGuard {
+public:
+    template <class F>
+    void run(F&& f) noexcept {
+        if (failed_.load(std::memory_order_relaxed)) return;
+        try {
+            f();
+        } catch (...) {
+            bool expected = false;
+            if (failed_.compare_exchange_strong(expected, true)) error_ = std::current_exception();
+        }
+    }
+    void rethrow() const {
+        if (failed_.load(std::memory_order_acquire)) std::rethrow_exception(error_);
+    }
+    bool failed() const { return failed_.load(std::memory_order_relaxed); }
+
+private:
+    std::atomic<bool> failed_{false};
+    std::exception_ptr error_;
+};
 
 // Allocator whose resize() leaves new elements uninitialised, so that large
 // arrays filled by parallel loops are not first zeroed by one thread.

@@ -152,11 +152,14 @@ Graph coarsen(const Graph& g, int32_t maxvw, uint64_t key, std::vector<int32_t>&
     Graph c;
     c.n = nc;
     c.vw.assign(nc, 0);
+    OmpGuard guard;
 #pragma omp parallel
     {
-        std::vector<int64_t> marker(nc, -1);
+        std::vector<int64_t> marker;
+        guard.run([&] { marker.assign(nc, -1); });
 #pragma omp for schedule(dynamic, 1024)
         for (int32_t ci = 0; ci < nc; ++ci) {
+            if (guard.failed()) continue;
             const int64_t start = ub[ci];
             int64_t end = start;
             const int32_t v = rep[ci], u = match[v];
@@ -179,6 +182,7 @@ Graph coarsen(const Graph& g, int32_t maxvw, uint64_t key, std::vector<int32_t>&
             cnt[ci] = (int32_t)(end - start);
         }
     }
+    guard.rethrow();
     c.xadj.assign(nc + 1, 0);
     for (int32_t ci = 0; ci < nc; ++ci) c.xadj[ci + 1] = c.xadj[ci] + cnt[ci];
     c.adj.resize(c.xadj[nc]);
@@ -365,7 +369,7 @@ void grow_and_refine(const Graph& g, int64_t target0, int64_t lo, int64_t hi, Rn
 }
 
 void bisect(const Graph& g, int64_t target0, int64_t lo, int64_t hi, Rng& rng,
-            std::vector<int8_t>& best_side) {
+            std::vector<int8_t>& best_side, OmpGuard& guard) {
     const int32_t n = g.n;
     const int trials = n > 20000 ? 3 : 6;
     std::vector<uint64_t> seeds(trials);
@@ -374,7 +378,7 @@ void bisect(const Graph& g, int64_t target0, int64_t lo, int64_t hi, Rng& rng,
     std::vector<int64_t> cut(trials), dev(trials);
     for (int t = 0; t < trials; ++t) {
 #pragma omp task default(shared) firstprivate(t) if (g.xadj[n] > 20000)
-        {
+        guard.run([&] {
             Rng r(seeds[t]);
             grow_and_refine(g, target0, lo, hi, r, sides[t]);
             int64_t wz = 0;
@@ -382,9 +386,10 @@ void bisect(const Graph& g, int64_t target0, int64_t lo, int64_t hi, Rng& rng,
                 if (sides[t][v] == 0) wz += g.vw[v];
             dev[t] = wz < lo ? lo - wz : (wz > hi ? wz - hi : 0);
             cut[t] = cut_2way(g, sides[t]);
-        }
+        });
     }
 #pragma omp taskwait
+    if (guard.failed()) return;
     int best = 0;
     for (int t = 1; t < trials; ++t)
         if (dev[t] < dev[best] || (dev[t] == dev[best] && cut[t] < cut[best])) best = t;
@@ -395,7 +400,7 @@ void bisect(const Graph& g, int64_t target0, int64_t lo, int64_t hi, Rng& rng,
 // Each node of the bisection tree seeds its own generator from (key, p0, k),
 // and the two halves run as separate tasks.
 void recursive_bisection(const Graph& g, const std::vector<int32_t>& ids, int32_t p0, int32_t k,
-                         uint64_t key, std::vector<int32_t>& part) {
+                         uint64_t key, std::vector<int32_t>& part, OmpGuard& guard) {
     if (k == 1 || g.n == 0) {
         for (int32_t v = 0; v < g.n; ++v) part[ids[v]] = p0;
         return;
@@ -408,15 +413,16 @@ void recursive_bisection(const Graph& g, const std::vector<int32_t>& ids, int32_
     for (int32_t w : g.vw) maxw = std::max(maxw, w);
     const int64_t delta = std::max<int64_t>(maxw, (int64_t)(0.003 * (double)W));
     std::vector<int8_t> side;
-    bisect(g, target0, std::max<int64_t>(0, target0 - delta), target0 + delta, rng, side);
+    bisect(g, target0, std::max<int64_t>(0, target0 - delta), target0 + delta, rng, side, guard);
+    if (guard.failed()) return;
     for (int8_t s = 0; s < 2; ++s) {
 #pragma omp task default(shared) firstprivate(s) if (g.n > 512)
-        {
+        guard.run([&] {
             std::vector<int32_t> loc_ids;
             Graph sub = induced(g, side, s, loc_ids);
             for (auto& v : loc_ids) v = ids[v];
-            recursive_bisection(sub, loc_ids, s == 0 ? p0 : p0 + k1, s == 0 ? k1 : k - k1, key, part);
-        }
+            recursive_bisection(sub, loc_ids, s == 0 ? p0 : p0 + k1, s == 0 ? k1 : k - k1, key, part, guard);
+        });
     }
 #pragma omp taskwait
 }
@@ -463,17 +469,19 @@ void refine_kway(const Graph& g, std::vector<int32_t>& part, int32_t nparts, int
     for (int pass = 0; pass < max_passes; ++pass) {
         int64_t moves = 0;
         for (int dir = 0; dir < 2; ++dir) {
+            OmpGuard guard;
 #pragma omp parallel num_threads(nt)
             {
-                std::vector<int64_t> conn(nparts, 0);
+                std::vector<int64_t> conn;
                 std::vector<int32_t> touched;
                 std::vector<Move>& mine = local[omp_get_thread_num()];
                 mine.clear();
+                guard.run([&] { conn.assign(nparts, 0); });
 #pragma omp for schedule(dynamic, 2048)
-                for (int32_t v = 0; v < g.n; ++v) {
+                for (int32_t v = 0; v < g.n; ++v) guard.run([&] {
                     const int32_t own = part[v];
                     const int64_t id = connectivity(g, part, v, conn, touched);
-                    if (touched.empty()) continue;
+                    if (touched.empty()) return;
                     int32_t best = -1;
                     int64_t best_ed = -1;
                     for (int32_t q : touched) {
@@ -485,12 +493,13 @@ void refine_kway(const Graph& g, std::vector<int32_t>& part, int32_t nparts, int
                         }
                     }
                     for (int32_t q : touched) conn[q] = 0;
-                    if (best < 0) continue;
+                    if (best < 0) return;
                     const int64_t gain = best_ed - id;
                     if (gain > 0 || (gain == 0 && pw[best] + g.vw[v] < pw[own]))
                         mine.push_back({v, best, gain});
-                }
+                });
             }
+            guard.rethrow();
             props.clear();
             for (auto& m : local) props.insert(props.end(), m.begin(), m.end());
             std::sort(props.begin(), props.end(), [](const Move& a, const Move& b) {
@@ -606,9 +615,11 @@ Error partition_multilevel(const Graph& g0, int32_t nparts, int64_t cap, uint64_
     {
         std::vector<int32_t> ids(cur->n);
         std::iota(ids.begin(), ids.end(), 0);
+        OmpGuard guard;
 #pragma omp parallel
 #pragma omp single
-        recursive_bisection(*cur, ids, 0, nparts, key, cpart);
+        guard.run([&] { recursive_bisection(*cur, ids, 0, nparts, key, cpart, guard); });
+        guard.rethrow();
     }
     balance(*cur, cpart, nparts, cap, rng);
     refine_kway(*cur, cpart, nparts, cap, 10);
