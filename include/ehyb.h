@@ -183,7 +183,10 @@ typedef struct {
  * ELL part: partition p's rows are cut into row-slices of C = 64/L rows,
  * slices [slice_start[p], slice_start[p+1]).  They are stored in the order a
  * workgroup takes them: first the ell_free[p] slices none of whose rows has
- * residual entries, then the others, each group by ascending row.
+ * residual entries, then the others, each group by ascending row.  Their slot
+ * ranges are placed round by round: queue positions 0..15 of every partition
+ * in partition order, then positions 16..31, and so on (any placement is
+ * valid; only the offsets say where a slice is).
  * ell_meta[4s..4s+3] = slot offset; width W, the entries each lane loads
  * (low 16 bits), and the slice's index j within its partition (high 16 bits:
  * row r of the slice is local row j*C + r); a 64-bit mask (low word, high

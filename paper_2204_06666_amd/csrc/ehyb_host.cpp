@@ -531,8 +531,28 @@ ehyb_status build_plan(const ehyb_csr_host* A, const std::vector<int32_t>& part,
     });
     guard.rethrow();
     P->ell_meta.assign((size_t)ns * 4, 0);
+    // Slot placement.  The kernel reads every slice's offset from its
+    // metadata, so the slices need not sit in partition order: they are laid
+    // out round by round, the first kPlaceRound slices (in queue order) of
+    // every partition, then the next kPlaceRound, and so on.  The slices that
+    // all workgroups read at about the same time then share one window of
+    // memory instead of forming one stream per workgroup, which a cold DRAM
+    // serves faster.
+    constexpr int32_t kPlaceRound = 16;
+    std::vector<int32_t> place, active(nparts);
+    place.reserve((size_t)ns);
+    for (int32_t p = 0; p < nparts; ++p) active[p] = p;
+    for (int32_t r = 0; !active.empty(); r += kPlaceRound) {
+        size_t keep = 0;
+        for (const int32_t p : active) {
+            const int32_t s1 = std::min(P->slice_start[p] + r + kPlaceRound, P->slice_start[p + 1]);
+            for (int32_t s = P->slice_start[p] + r; s < s1; ++s) place.push_back(s);
+            if (s1 < P->slice_start[p + 1]) active[keep++] = p;
+        }
+        active.resize(keep);
+    }
     int64_t eoff = 0;
-    for (int32_t s = 0; s < ns; ++s) {
+    for (int32_t s : place) {
         if (eoff > UINT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^32 slots in the ELL part");
         if (ell_steps[s] > 65535) return fail(EHYB_EUNSUPPORTED, "ELL row-slice wider than 65535 entries per lane");
         P->ell_meta[4 * (size_t)s + 0] = (uint32_t)eoff;
