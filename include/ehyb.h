@@ -313,10 +313,13 @@ EHYB_API ehyb_status ehyb_unpermute_y(const ehyb_plan *plan, const void *y_perm,
  *
  * A batch groups uploaded plans of one value type, one rows_per_wave and one
  * n_rhs.  ehyb_spmm_batched computes Y_i = A_i X_i for every matrix i in one
- * persistent kernel launch: workgroups take (matrix, partition) items, largest
- * first, from a queue in the batch's device blob (the global queue of Alg. 3,
- * spread over matrices); the last workgroup to finish resets the queue, so
- * the launch can be recorded in a HIP graph and replayed.  X_i and Y_i are
+ * persistent kernel launch: workgroups take (matrix, partition) items from
+ * queues in the batch's device blob (the global queue of Alg. 3, spread over
+ * matrices): the items, by matrix and then partition, are cut into eight runs
+ * of about equal bytes, one per XCD, so that neighbouring partitions, which
+ * share halo rows of x, run on one XCD's L2; a workgroup whose run is empty
+ * takes items from the other runs.  The last workgroup to finish resets the
+ * queues, so the launch can be recorded in a HIP graph and replayed.  X_i and Y_i are
  * row-major [n_i][n_rhs] in plan i's permuted order (flag EHYB_VEC_PERMUTED
  * required), element type as for ehyb_spmv. */
 typedef struct ehyb_batch ehyb_batch;

@@ -89,11 +89,17 @@ struct SpmvArgs {
     void* y;                        // permuted order
 };
 
+// The batched product's work queue is split in one queue per XCD: queue k
+// hands out the items [range[k], range[k+1]) in order, and its counter sits
+// on a cache line of its own.
+constexpr int kCtrStride = 32;  // ints between two queue counters (128 bytes)
+
 struct BatchArgs {
     const PartArrays* mats;         // [n_mats]
-    const int2* items;              // (matrix, partition), largest first
+    const int2* items;              // (matrix, partition), by matrix, then partition
     int32_t n_items;
-    int32_t* counters;              // [0] next item, [1] workgroups finished
+    int32_t range[kXcds + 1];       // items of each XCD's queue
+    int32_t* counters;              // [k * kCtrStride] next item of queue k; [kXcds * kCtrStride] workgroups finished
     const void* X[EHYB_BATCH_MAX];  // row-major [n_i][NRHS], permuted order
     void* Y[EHYB_BATCH_MAX];
 };
@@ -683,9 +689,15 @@ __global__ void __launch_bounds__(1024) ehyb_spmv_kernel(SpmvArgs a) {
 }
 
 // Y_i = A_i X_i for a batch: persistent workgroups take (matrix, partition)
-// items from a global queue, largest first (the global queue of Alg. 3,
-// spread over matrices).  The last workgroup to leave resets the queue, so the
-// next launch (or graph replay) starts from zero.
+// items from a queue (the global queue of Alg. 3, spread over matrices), first
+// from their own XCD's queue, then, once it is empty, from the other XCDs'
+// queues in turn.  Each XCD's queue holds a contiguous run of items in
+// partition order: partitions numbered close together are neighbours (the
+// partitioner bisects recursively), so the x rows one partition loads as its
+// halo are mostly those its neighbours load as theirs or as their x-slice,
+// on the same XCD at about the same time, and are found in that XCD's L2.
+// The last workgroup to leave resets the counters, so the next launch (or
+// graph replay) starts from zero.
 template <int DT, int L, int NRHS, bool NT>
 __global__ void __launch_bounds__(1024) ehyb_spmm_batched_kernel(BatchArgs args) {
     using X = typename Prec<DT>::X;
@@ -698,12 +710,25 @@ __global__ void __launch_bounds__(1024) ehyb_spmm_batched_kernel(BatchArgs args)
     __shared__ Queues Q;
     __shared__ int s_item;
     int32_t* counters = a.counters;
-    const int n_items = a.n_items;
+    const int home = (int)(blockIdx.x % kXcds);
+    int visited = 0;  // queues found empty so far (used by thread 0 only)
     for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(&counters[0], 1);
+        if (threadIdx.x == 0) {
+            int it = -1;
+            while (visited < kXcds) {
+                const int q = (home + visited) % kXcds;
+                const int i = atomicAdd(&counters[q * kCtrStride], 1);
+                if (i < a.range[q + 1] - a.range[q]) {
+                    it = a.range[q] + i;
+                    break;
+                }
+                ++visited;
+            }
+            s_item = it;
+        }
         __syncthreads();
         const int it = s_item;
-        if (it >= n_items) break;
+        if (it < 0) break;
         const int2 w = a.items[it];
         const int mi = __builtin_amdgcn_readfirstlane(w.x);
         const int pi = __builtin_amdgcn_readfirstlane(w.y);
@@ -711,9 +736,11 @@ __global__ void __launch_bounds__(1024) ehyb_spmm_batched_kernel(BatchArgs args)
                                        static_cast<X*>(a.Y[mi]), lds_raw, Q);
         __syncthreads();  // LDS, Q and s_item are reused by the next item
     }
-    if (threadIdx.x == 0 && atomicAdd(&counters[1], 1) == (int)gridDim.x - 1) {
-        __hip_atomic_store(&counters[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(&counters[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // Every workgroup has seen all queues empty before it counts itself
+    // here, and waited for the result of each of its queue increments.
+    if (threadIdx.x == 0 && atomicAdd(&counters[kXcds * kCtrStride], 1) == (int)gridDim.x - 1) {
+        for (int q = 0; q <= kXcds; ++q)
+            __hip_atomic_store(&counters[q * kCtrStride], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -1230,12 +1257,14 @@ ehyb_status ehyb_batch_create(const ehyb_plan* const* plans, int32_t n_plans, in
         }
         if (B->L != 1 && B->L != 4 && B->L != 16)
             return fail(EHYB_EUNSUPPORTED, "batched products support rows_per_wave 64, 16 or 4");
-        // work items, largest first: bytes each partition streams
+        // work items by matrix, then partition, with the bytes each streams;
+        // cut into one run per XCD queue of about equal bytes
         struct Item {
             int64_t cost;
             int32_t m, p;
         };
         std::vector<Item> items;
+        int64_t total_cost = 0;
         for (int32_t i = 0; i < n_plans; ++i) {
             const ehyb_plan& P = *B->plans[i];
             for (int32_t p = 0; p < P.nparts; ++p) {
@@ -1246,17 +1275,25 @@ ehyb_status ehyb_batch_create(const ehyb_plan* const* plans, int32_t n_plans, in
                     c += (int64_t)P.er_meta[2 * (size_t)e + 1] * kWave * (P.vbytes + 4);
                 c += 2LL * (P.part_start[p + 1] - P.part_start[p]) * P.xbytes * n_rhs;
                 items.push_back({c, i, p});
+                total_cost += c;
             }
             B->lds_bytes = std::max<int64_t>(B->lds_bytes, lds_bytes_used(P, n_rhs));
             B->algorithmic_bytes += algorithmic_bytes(P) + 2LL * (n_rhs - 1) * P.n * P.xbytes;
         }
         if (B->lds_bytes > 160 * 1024 - kStaticLds) return fail(EHYB_EINVAL, "a plan needs more LDS than a workgroup has");
-        std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+        if (items.size() > (size_t)INT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^31 work items");
         B->items.reserve(items.size() * 2);
-        for (const Item& it : items) {
-            B->items.push_back(it.m);
-            B->items.push_back(it.p);
+        B->range.assign(kXcds + 1, 0);
+        int64_t run = 0;
+        int32_t q = 1;
+        for (size_t k = 0; k < items.size(); ++k) {
+            // item k starts queue q once the items before it hold q/8 of the bytes
+            while (q < kXcds && run * kXcds >= total_cost * q) B->range[q++] = (int32_t)k;
+            B->items.push_back(items[k].m);
+            B->items.push_back(items[k].p);
+            run += items[k].cost;
         }
+        while (q <= kXcds) B->range[q++] = (int32_t)items.size();
         size_t off = 0;
         auto take = [&](size_t bytes) {
             size_t at = off;
@@ -1265,7 +1302,7 @@ ehyb_status ehyb_batch_create(const ehyb_plan* const* plans, int32_t n_plans, in
         };
         B->off_desc = take(sizeof(PartArrays) * (size_t)n_plans);
         B->off_items = take(B->items.size() * 4);
-        B->off_counters = take(2 * sizeof(int32_t));
+        B->off_counters = take((kXcds + 1) * kCtrStride * sizeof(int32_t));
         B->total = off;
         *out = B.release();
         return EHYB_OK;
@@ -1291,12 +1328,13 @@ ehyb_status ehyb_batch_upload(ehyb_batch* B, void* dev_blob, size_t bytes, void*
     }
     hipStream_t s = (hipStream_t)stream;
     char* b = (char*)dev_blob;
-    const int32_t zeros[2] = {0, 0};
+    const std::vector<int32_t> zeros((kXcds + 1) * kCtrStride, 0);
     hipError_t e = hipMemcpyAsync(b + B->off_desc, desc.data(), desc.size() * sizeof(PartArrays),
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess && !B->items.empty())
         e = hipMemcpyAsync(b + B->off_items, B->items.data(), B->items.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b + B->off_counters, zeros, sizeof(zeros), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b + B->off_counters, zeros.data(), zeros.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(EHYB_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
     B->dev_blob = dev_blob;
@@ -1316,6 +1354,7 @@ ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* co
     a.items = (const int2*)(b + B->off_items);
     a.n_items = (int32_t)(B->items.size() / 2);
     a.counters = (int32_t*)(b + B->off_counters);
+    for (int q = 0; q <= kXcds; ++q) a.range[q] = B->range[q];
     const size_t eb = (B->value_dtype == EHYB_F64 ? 8 : 4);
     for (size_t i = 0; i < B->plans.size(); ++i) {
         if (!X[i] || !Y[i]) return fail(EHYB_EINVAL, "null vector in batch");

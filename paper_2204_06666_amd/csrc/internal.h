@@ -183,7 +183,8 @@ struct ehyb_plan {
 struct ehyb_batch {
     std::vector<const ehyb_plan*> plans;
     int32_t n_rhs = 1, value_dtype = EHYB_F64, L = 1;
-    std::vector<int32_t> items;      // (matrix, partition) pairs, largest first
+    std::vector<int32_t> items;      // (matrix, partition) pairs, by matrix, then partition
+    std::vector<int32_t> range;      // [9] items of each XCD's queue
     size_t off_desc = 0, off_items = 0, off_counters = 0, total = 0;
     void* dev_blob = nullptr;
     int64_t lds_bytes = 0;           // dynamic LDS of one workgroup
