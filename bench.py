@@ -719,24 +719,27 @@ def run_batched(args):
 
 
 def run_powerlaw(args):
-    """Power-law graphs (Chung-Lu) with hub rows of 10^4 entries, default
-    plans, FP64 and FP32 values: EHYB (hub rows summed over the whole device
-    before the product) against the plain CSR kernel on the same GPU, each
-    checked against scipy's FP64 product."""
+    """Power-law graphs (Chung-Lu) with hub rows of 10^4-10^5 entries, FP64
+    and FP32 values, default plans (hub rows summed over the whole device
+    before the product), plus the FP64 plan with a 64-entry ELL cap: EHYB
+    against the plain CSR kernel and rocSPARSE on the same GPU, each checked
+    against scipy's FP64 product.  The roofline is the FP64 default plan of
+    the larger graph (both kernels of one product)."""
     import numpy as np
     import torch
 
     import matgen
     from paper_2204_06666_amd import EHYB_F32, EHYB_F64, Plan, csr_spmv
+    from paper_2204_06666_amd.workloads import POWERLAW
 
     dev = torch.device("cuda:0")
-    cases = [("n=6e4 exponent 2.2 mean degree 30", dict(n=60000, exponent=2.2, mean_deg=30, seed=5)),
-             ("n=2.5e5 exponent 2.1 mean degree 40", dict(n=250000, exponent=2.1, mean_deg=40, seed=7))]
+    cases = [("n=6e4 exponent 2.2 mean degree 30", dict(n=60000, exponent=2.2, mean_deg=30, seed=5), 3),
+             ("n=2.5e5 exponent 2.1 mean degree 40", POWERLAW["matgen"], POWERLAW["x_seed"])]
     res = []
-    for desc, kw in cases:
+    for desc, kw, xs in cases:
         log(f"generating power-law {desc}")
         A = matgen.powerlaw(**kw)
-        x = matgen.uniform_vector(A.n_rows, 3)
+        x = matgen.uniform_vector(A.n_rows, xs)
         y64, s64 = fp64_products(A.row_ptr, A.col, A.val, x)
         rp = torch.from_numpy(A.row_ptr.astype(np.int32)).to(dev)
         ci = torch.from_numpy(A.col).to(dev)
@@ -745,12 +748,14 @@ def run_powerlaw(args):
         yo = torch.empty_like(xo)
         csr = {lanes: time_launches(torch, lambda: csr_spmv(rp, ci, cv, xo, yo, lanes), args.steps, args.warmup)[0]
                for lanes in (4, 8, 16, 32)}
+        _, rs_k, _, rs_err = rocsparse_time(torch, A.row_ptr, A.col, A.val, xo, args.steps, args.warmup)
         row = {"matrix": desc, "n": int(A.n_rows), "nnz": int(A.nnz),
                "max_row": int(np.diff(A.row_ptr).max()),
-               "csr_best_us": round(min(csr.values()) * 1e6, 2)}
-        for name, dt in (("f64", EHYB_F64), ("f32", EHYB_F32)):
+               "csr_best_us": round(min(csr.values()) * 1e6, 2),
+               "rocsparse_us": round(rs_k * 1e6, 2) if rs_k else rs_err}
+        for name, dt, cap in (("f64", EHYB_F64, 0), ("f32", EHYB_F32, 0), ("f64_cap64", EHYB_F64, 64)):
             t0 = time.perf_counter()
-            plan = Plan(A, value_dtype=dt).upload(dev)
+            plan = Plan(A, value_dtype=dt, ell_width_cap=cap).upload(dev)
             t_pre = time.perf_counter() - t0
             st = plan.stats()
             xp = torch.from_numpy(x[plan.perm()].astype(np.float64 if dt == EHYB_F64 else np.float32)).to(dev)
@@ -759,18 +764,36 @@ def run_powerlaw(args):
             y = np.empty(A.n_rows)
             y[plan.perm()] = yp.cpu().numpy()
             row[name] = {"us": round(wall * 1e6, 2), "GFLOPs": round(2.0 * A.nnz / wall / 1e9, 2),
+                         "algorithmic_bytes": st["algorithmic_bytes"],
+                         "frac_of_8TBps": round(st["algorithmic_bytes"] / wall / 8e12, 4),
                          "nparts": st["nparts"], "nnz_er": st["nnz_er"], "n_er_wide": st["n_er_wide"],
-                         "n_er_pieces": st["n_er_pieces"], "preprocess_s": round(t_pre, 2),
+                         "n_er_pieces": st["n_er_pieces"], "max_halo": st["max_halo"],
+                         "preprocess_s": round(t_pre, 2),
                          "max_row_scaled_error_vs_fp64": float(scaled_error(y, y64, s64).max())}
             del plan, xp, yp
         row["speedup_f64_vs_csr"] = round(row["csr_best_us"] / row["f64"]["us"], 2)
         log(f"{row}")
         res.append(row)
-    out = {"metric": "EHYB SpMV on power-law graphs with hub rows, us per product", "value": res[-1]["f64"]["us"],
+        last = (A, x)
+    big = res[-1]["f64"]
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("CPU oracle baseline")
+        A, x = last
+        cpu = cpu_oracle_baseline(oracle, A, x, 2.0 * A.nnz, "the whole 2.5e5-row power-law graph")
+    out = {"metric": "EHYB SpMV on power-law graphs with hub rows, us per product", "value": big["us"],
            "unit": "us", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_per_step": round(res[-1]["f64"]["us"] / 1e3, 5), "higher_is_better": False, "scaling": "weak",
+           "ms_per_step": round(big["us"] / 1e3, 5), "higher_is_better": False, "scaling": "weak",
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-           "config": {"workload": "Chung-Lu power-law graphs, default plans"}, "matrices": res}
+           "config": {"workload": POWERLAW["workload"]},
+           "roofline": {"bound": "hbm", "achieved": round(big["algorithmic_bytes"] / big["us"] / 1e3, 1),
+                        "peak": PEAK_HBM_GBPS, "unit": "GB/s", "frac": big["frac_of_8TBps"],
+                        "traffic": load_traffic(kernel_source_hash(), "ehyb_spmv_f64_powerlaw250k_traffic.json"),
+                        "kernel": "er_pieces_kernel<EHYB_F64> + ehyb_spmv_kernel<EHYB_F64, L=1, plain loads> "
+                                  "(one product)",
+                        "algorithmic_bytes": big["algorithmic_bytes"], "launch_us": big["us"]},
+           "cpu_baseline": cpu, "matrices": res}
     print(json.dumps(out), flush=True)
 
 

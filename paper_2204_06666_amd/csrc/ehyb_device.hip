@@ -48,8 +48,10 @@ struct PartArrays {
     const uint16_t* er_row;         // local row of each residual slice row, 0xFFFF = none
     // Wide residual slices summed beforehand (ehyb_spmv, one right-hand side):
     // slice e's pieces are er_piece[e] .. er_piece[e+1]-1, their sums in
-    // er_part.  Null: every slice is summed by its partition's workgroup.
+    // er_part; the first er_nwide[p] residual slices of partition p are the
+    // wide ones.  Null: every slice is summed by its partition's workgroup.
     const int32_t* er_piece;
+    const int32_t* er_nwide;
     const void* er_part;
     const void* ell_val;            // value type of the plan
     const uint16_t* ell_col;
@@ -79,6 +81,7 @@ PartArrays part_arrays(const ehyb_plan& P) {
     a.lds_rows = P.max_part_rows + P.max_halo;
     a.n = (int32_t)P.n;
     a.er_piece = nullptr;
+    a.er_nwide = nullptr;
     a.er_part = nullptr;
     return a;
 }
@@ -105,6 +108,7 @@ struct BatchArgs {
 };
 
 constexpr int kErChunk = 16;    // residual steps whose loads are issued before any is used
+constexpr int kPieceLoads = 8;  // pieces of a wide slice each lane loads per round
 constexpr int kStageRegs = 4;   // x-slice rows per thread kept in flight
 constexpr int kHaloRegs = 4;    // halo gathers per thread kept in flight
 
@@ -302,11 +306,12 @@ __device__ __forceinline__ int wave_fetch_add(int* ctr, int lane) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
-// Release this wave's LDS writes, then count it in `ctr`.
-__device__ __forceinline__ void wave_signal(int* ctr, int lane) {
+// Release this wave's LDS writes, then count it in `ctr` (`n` times).
+__device__ __forceinline__ void wave_signal_n(int* ctr, int lane, int n) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (lane == 0) atomicAdd(ctr, 1);
+    if (lane == 0) atomicAdd(ctr, n);
 }
+__device__ __forceinline__ void wave_signal(int* ctr, int lane) { wave_signal_n(ctr, lane, 1); }
 
 // Wait (sleeping) until `ctr` reaches `target`, then acquire the LDS writes
 // released before each increment.  Every increment is made by a wavefront of
@@ -519,12 +524,6 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
         XR hv[kHaloRegs];
 #pragma unroll
         for (int j = 0; j < kHaloRegs; ++j) hv[j] = buf_load<XR>(r_x, (has_halo ? hi[j] : own_last) * (uint32_t)sizeof(XR));
-        // partitions or halos beyond the registers' reach (large LDS budgets):
-        // the rest, row by row, before the first slice's loads are issued
-        for (int i = tid + kStageRegs * nthr; i < sz; i += nthr)
-            xsr[i] = buf_load<XR>(r_xs, (uint32_t)i * (uint32_t)sizeof(XR));
-        for (int i = tid + kHaloRegs * nthr; i < hn; i += nthr)
-            xsr[sz + i] = buf_load<XR>(r_x, buf_load<uint32_t>(r_hidx, (uint32_t)i * 4u) * (uint32_t)sizeof(XR));
         // The first ELL slice's first round, after the gathers, so that
         // waiting for the gathers does not wait for it.  Issued by every
         // wavefront, without a branch: one without a first slice reads
@@ -539,6 +538,30 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
 #pragma unroll
         for (int j = 0; j < kHaloRegs; ++j)
             xsr[has_halo ? sz + min((uint32_t)(tid + j * nthr), hn_last) : sz_last] = hv[j];
+        // Partitions or halos beyond that first pass (large LDS budgets, the
+        // long halos of power-law matrices): the rest in chunks of kRest rows
+        // per thread, each chunk's loads (index loads, then gathers) issued
+        // before any of its stores, with the same clamping.
+        constexpr int kRest = NRHS == 1 ? 8 : kHaloRegs;
+        for (uint32_t b = (uint32_t)(kStageRegs * nthr); b < (uint32_t)sz; b += (uint32_t)(kRest * nthr)) {
+            XR v2[kRest];
+#pragma unroll
+            for (int j = 0; j < kRest; ++j)
+                v2[j] = buf_load<XR>(r_xs, min(b + (uint32_t)(tid + j * nthr), sz_last) * (uint32_t)sizeof(XR));
+#pragma unroll
+            for (int j = 0; j < kRest; ++j) xsr[min(b + (uint32_t)(tid + j * nthr), sz_last)] = v2[j];
+        }
+        for (uint32_t b = (uint32_t)(kHaloRegs * nthr); b < (uint32_t)hn; b += (uint32_t)(kRest * nthr)) {
+            uint32_t h2[kRest];
+#pragma unroll
+            for (int j = 0; j < kRest; ++j)
+                h2[j] = buf_load<uint32_t>(r_hidx, min(b + (uint32_t)(tid + j * nthr), hn_last) * 4u);
+            XR v2[kRest];
+#pragma unroll
+            for (int j = 0; j < kRest; ++j) v2[j] = buf_load<XR>(r_x, h2[j] * (uint32_t)sizeof(XR));
+#pragma unroll
+            for (int j = 0; j < kRest; ++j) xsr[sz + min(b + (uint32_t)(tid + j * nthr), hn_last)] = v2[j];
+        }
     }
     bool er_ready = ner == 0;
     // the rest of a slice after its first round, the residual sums of its
@@ -585,54 +608,79 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
         ell_finish(m_first, kPre, acc);
     }
 
-    // 2. residual queue
+    // 2. residual queue.  When the wide slices (which lead the partition's
+    // residual slices) were summed beforehand in pieces, their items are
+    // groups of 64 slices, one per lane, each lane adding its slice's pieces
+    // in piece order; the other items are single slices.
     {
         const V* er_val = static_cast<const V*>(a.er_val);
-        const XR* xr = reinterpret_cast<const XR*>(x);
+        const Rsrc r_xg = make_rsrc(x, (uint32_t)((size_t)a.n * sizeof(XR)));
         const i32x4 r_meta = scalar_rsrc(a.er_meta + e0, (uint32_t)ner * 8u);
+        const int nw = (NRHS == 1 && a.er_piece != nullptr) ? a.er_nwide[p] : 0;
+        const int ngr = (nw + kWave - 1) / kWave;
+        const int nitems = ngr + ner - nw;
+        // residual slice of item i >= ngr (clamped below for group items, whose metadata is not used)
+        auto slice_of = [&](int i) { return (uint32_t)max(i - ngr + nw, 0); };
         int it = wave_fetch_add(&Q.q_er, lane);
-        uint2 m = sload2(r_meta, (uint32_t)it * 8u);
-        while (it < ner) {
+        uint2 m = sload2(r_meta, slice_of(it) * 8u);
+        while (it < nitems) {
             const int itn = wave_fetch_add(&Q.q_er, lane);
-            const uint2 mn = sload2(r_meta, (uint32_t)itn * 8u);
-            const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
-            const uint32_t my = __builtin_amdgcn_readfirstlane(m.y);
-            const uint32_t steps = my & ~kErWide;
-            const bool wide = (my & kErWide) != 0;  // one long row on all 64 lanes
-            const V* ev = er_val + off + lane;
-            const int32_t* ec = a.er_col + off + lane;
-            const uint16_t lr = a.er_row[(size_t)(e0 + it) * C + (wide ? 0 : r)];
+            const uint2 mn = sload2(r_meta, slice_of(itn) * 8u);
             if constexpr (NRHS == 1) {
-                if (wide && a.er_piece != nullptr) {
-                    // summed beforehand in pieces: add them in piece order
-                    const int q0 = __builtin_amdgcn_readfirstlane(a.er_piece[e0 + it]);
-                    const int q1 = __builtin_amdgcn_readfirstlane(a.er_piece[e0 + it + 1]);
-                    const Acc* part = static_cast<const Acc*>(a.er_part);
+                if (it < ngr) {
+                    const int k = it * kWave + lane;  // this lane's wide slice
+                    const int e = e0 + min(k, nw - 1);
+                    const int q0 = a.er_piece[e];
+                    const int nq = a.er_piece[e + 1] - q0;  // at least 1
+                    const uint16_t lw = a.er_row[(size_t)e * C];
+                    const Acc* part = static_cast<const Acc*>(a.er_part) + q0;
                     Acc sum = 0;
-                    for (int q = q0; q < q1; ++q) sum += part[q];
-                    if (lane == 0 && lr != 0xFFFF) yer[lr] = sum;
-                    wave_signal(&Q.n_er_done, lane);
+                    // all lanes load kPieceLoads pieces per round (clamped to
+                    // their last piece), so the loads are issued together
+                    for (int j0 = 0; __builtin_amdgcn_ballot_w64(j0 < nq) != 0; j0 += kPieceLoads) {
+                        Acc pv[kPieceLoads];
+#pragma unroll
+                        for (int u = 0; u < kPieceLoads; ++u) pv[u] = part[min(j0 + u, nq - 1)];
+#pragma unroll
+                        for (int u = 0; u < kPieceLoads; ++u)
+                            if (j0 + u < nq) sum += pv[u];
+                    }
+                    if (k < nw && lw != 0xFFFF) yer[lw] = sum;
+                    wave_signal_n(&Q.n_er_done, lane, min(kWave, nw - it * kWave));
                     it = itn;
                     m = mn;
                     continue;
                 }
             }
+            const int es = (int)slice_of(it);
+            const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
+            const uint32_t my = __builtin_amdgcn_readfirstlane(m.y);
+            const uint32_t steps = my & ~kErWide;
+            const bool wide = (my & kErWide) != 0;  // one long row on all 64 lanes
+            const uint16_t lr = a.er_row[(size_t)(e0 + es) * C + (wide ? 0 : r)];
             Acc acc[NRHS];
 #pragma unroll
             for (int k = 0; k < NRHS; ++k) acc[k] = 0;
+            // Every load of a batch of kEr steps is issued unconditionally
+            // (through views of the slice: a step past its end reads column
+            // 0 and value 0 without a memory access, and gathers x[0]); only
+            // the multiply-adds of real steps are guarded.  A load under a
+            // branch is waited for at the branch's end, which would issue the
+            // steps' gathers one round trip at a time.
+            const Rsrc r_ec = make_rsrc(a.er_col + off, steps * (uint32_t)(kWave * sizeof(int32_t)));
+            const Rsrc r_ev = make_rsrc(er_val + off, steps * (uint32_t)(kWave * sizeof(V)));
             for (uint32_t t0 = 0; t0 < steps; t0 += kEr) {
                 int32_t c[kEr];
                 V v[kEr];
                 XR xg[kEr];
 #pragma unroll
-                for (int j = 0; j < kEr; ++j)
-                    if (t0 + j < steps) {
-                        c[j] = ld<NT>(ec + (size_t)(t0 + j) * kWave);
-                        v[j] = ld<NT>(ev + (size_t)(t0 + j) * kWave);
-                    }
+                for (int j = 0; j < kEr; ++j) {
+                    c[j] = buf_load<int32_t, NT>(r_ec, lane * (uint32_t)sizeof(int32_t),
+                                                 (t0 + j) * (uint32_t)(kWave * sizeof(int32_t)));
+                    v[j] = buf_load<V, NT>(r_ev, lane * (uint32_t)sizeof(V), (t0 + j) * (uint32_t)(kWave * sizeof(V)));
+                }
 #pragma unroll
-                for (int j = 0; j < kEr; ++j)
-                    if (t0 + j < steps) xg[j] = xr[c[j]];
+                for (int j = 0; j < kEr; ++j) xg[j] = buf_load<XR>(r_xg, (uint32_t)c[j] * (uint32_t)sizeof(XR));
 #pragma unroll
                 for (int j = 0; j < kEr; ++j)
                     if (t0 + j < steps) {
@@ -750,13 +798,18 @@ __global__ void __launch_bounds__(1024) ehyb_spmm_batched_kernel(BatchArgs args)
 // (e, t0, t1) holds slots off + 64*t0 .. off + 64*t1 - 1, one per lane per
 // step; each lane sums its entries in step order, then the wavefront adds
 // its lanes in a fixed tree.  The partition's workgroup adds the pieces of
-// its row in piece order, so results do not depend on timing.
+// its row in a fixed order, so results do not depend on timing.  All loads
+// are issued unconditionally through views of the piece (steps past its end
+// read column 0 and value 0 without a memory access, and gather x[0]), so
+// that the gathers are in flight together; only the multiply-adds of real
+// steps are guarded.
 template <int DT, bool NT>
 __global__ void __launch_bounds__(256) er_pieces_kernel(const uint2* __restrict__ er_meta,
                                                         const void* __restrict__ er_val_,
                                                         const int32_t* __restrict__ er_col,
                                                         const int32_t* __restrict__ pieces, int n_pieces,
-                                                        const void* __restrict__ x_, void* __restrict__ part_) {
+                                                        const void* __restrict__ x_, uint32_t x_bytes,
+                                                        void* __restrict__ part_) {
     using P = Prec<DT>;
     using V = typename P::V;
     using X = typename P::X;
@@ -769,19 +822,21 @@ __global__ void __launch_bounds__(256) er_pieces_kernel(const uint2* __restrict_
     const int e = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q]);
     const int t0 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 1]);
     const int t1 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 2]);
-    const size_t base = (size_t)__builtin_amdgcn_readfirstlane(er_meta[e].x) + lane;
+    const size_t base = (size_t)__builtin_amdgcn_readfirstlane(er_meta[e].x) + (size_t)t0 * kWave;
+    const uint32_t nst = (uint32_t)(t1 - t0);
+    const Rsrc rc = make_rsrc(er_col + base, nst * (uint32_t)(kWave * sizeof(int32_t)));
+    const Rsrc rv = make_rsrc(er_val + base, nst * (uint32_t)(kWave * sizeof(V)));
+    const Rsrc rx = make_rsrc(x, x_bytes);
     int32_t c[kPieceSteps];
     V v[kPieceSteps];
 #pragma unroll
-    for (int j = 0; j < kPieceSteps; ++j)
-        if (t0 + j < t1) {
-            c[j] = ld<NT>(er_col + base + (size_t)(t0 + j) * kWave);
-            v[j] = ld<NT>(er_val + base + (size_t)(t0 + j) * kWave);
-        }
+    for (int j = 0; j < kPieceSteps; ++j) {
+        c[j] = buf_load<int32_t, NT>(rc, lane * (uint32_t)sizeof(int32_t), (uint32_t)j * (uint32_t)(kWave * sizeof(int32_t)));
+        v[j] = buf_load<V, NT>(rv, lane * (uint32_t)sizeof(V), (uint32_t)j * (uint32_t)(kWave * sizeof(V)));
+    }
     X xg[kPieceSteps];
 #pragma unroll
-    for (int j = 0; j < kPieceSteps; ++j)
-        if (t0 + j < t1) xg[j] = x[c[j]];
+    for (int j = 0; j < kPieceSteps; ++j) xg[j] = buf_load<X>(rx, (uint32_t)c[j] * (uint32_t)sizeof(X));
     Acc acc = 0;
 #pragma unroll
     for (int j = 0; j < kPieceSteps; ++j)
@@ -799,12 +854,13 @@ void launch_pieces(const ehyb_plan& P, bool nt, const void* x, hipStream_t s) {
     const int32_t* col = (const int32_t*)(blob + Ly.er_col);
     const int32_t* pc = (const int32_t*)(blob + Ly.pieces);
     void* part = (void*)(blob + Ly.ypart);
+    const uint32_t xb = (uint32_t)((size_t)P.n * P.xbytes);  // below 4 GiB: checked by ehyb_spmv
     if (nt)
         hipLaunchKernelGGL((er_pieces_kernel<DT, true>), dim3(nblocks), dim3(256), 0, s, meta, blob + Ly.er_val, col, pc,
-                           P.n_pieces, x, part);
+                           P.n_pieces, x, xb, part);
     else
         hipLaunchKernelGGL((er_pieces_kernel<DT, false>), dim3(nblocks), dim3(256), 0, s, meta, blob + Ly.er_val, col,
-                           pc, P.n_pieces, x, part);
+                           pc, P.n_pieces, x, xb, part);
 }
 
 // Plain CSR SpMV, the comparator (CSR-vector): L lanes per row, rows of a
@@ -1105,6 +1161,7 @@ ehyb_status ehyb_plan_upload(ehyb_plan* P, void* dev_blob, size_t bytes, void* s
         {L.er_col, P->er_col.data(), P->er_col.size() * 4},
         {L.perm, P->perm.data(), P->perm.size() * 4},
         {L.piece_start, P->piece_start.data(), P->piece_start.size() * 4},
+        {L.piece_nwide, P->piece_nwide.data(), P->piece_nwide.size() * 4},
         {L.pieces, P->pieces.data(), P->pieces.size() * 4},
     };
     for (const Piece& pc : pieces) {
@@ -1215,6 +1272,7 @@ ehyb_status ehyb_spmv(const ehyb_plan* P, const void* x, void* y, uint32_t flags
             default: return fail(EHYB_EINVAL, "bad value type");
         }
         a.m.er_piece = (const int32_t*)(blob + Ly.piece_start);
+        a.m.er_nwide = (const int32_t*)(blob + Ly.piece_nwide);
         a.m.er_part = blob + Ly.ypart;
     }
     bool ok = false;

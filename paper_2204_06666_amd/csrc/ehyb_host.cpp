@@ -228,7 +228,7 @@ int64_t algorithmic_bytes(const ehyb_plan& p) {
     b += p.n * p.xbytes;                               // x, each element once (slice staging)
     b += p.n * p.xbytes;                               // y, written once
     if (p.n_pieces > 0)                                // wide slices in pieces: piece list,
-        b += (int64_t)(p.ner_slices + 1) * 4 + (int64_t)p.n_pieces * (12 + 2 * 8);  // partial sums out and in
+        b += (int64_t)(p.ner_slices + 1 + p.nparts) * 4 + (int64_t)p.n_pieces * (12 + 2 * 8);  // partial sums out and in
     return b;
 }
 
@@ -258,6 +258,7 @@ BlobLayout compute_layout(const ehyb_plan& p) {
     L.yp = take((size_t)p.n * p.xbytes);
     if (p.n_pieces > 0) {
         L.piece_start = take((size_t)(p.ner_slices + 1) * 4);
+        L.piece_nwide = take((size_t)p.nparts * 4);
         L.pieces = take((size_t)p.n_pieces * 12);
         L.ypart = take((size_t)p.n_pieces * 8);
     }
@@ -295,7 +296,17 @@ void build_pieces(ehyb_plan& P) {
     }
     P.piece_start[P.ner_slices] = q;
     P.n_pieces = q;
-    if (q == 0) P.piece_start.clear();
+    // wide slices lead each partition's residual slices: count that run
+    P.piece_nwide.assign((size_t)P.nparts, 0);
+    for (int32_t p = 0; p < P.nparts; ++p) {
+        int32_t e = P.er_slice_start[p];
+        while (e < P.er_slice_start[p + 1] && (P.er_meta[2 * (size_t)e + 1] & kErWide)) ++e;
+        P.piece_nwide[p] = e - P.er_slice_start[p];
+    }
+    if (q == 0) {
+        P.piece_start.clear();
+        P.piece_nwide.clear();
+    }
 }
 
 // Residual position of every permuted row (e*C + r, or -1), from er_row.

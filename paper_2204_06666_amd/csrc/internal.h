@@ -127,7 +127,7 @@ struct BlobLayout {
     size_t ell_meta = 0, er_meta = 0, er_row = 0;
     size_t ell_val = 0, ell_col = 0, er_val = 0, er_col = 0;
     size_t perm = 0, xp = 0, yp = 0;
-    size_t piece_start = 0, pieces = 0, ypart = 0;  // wide residual slices in pieces
+    size_t piece_start = 0, piece_nwide = 0, pieces = 0, ypart = 0;  // wide residual slices in pieces
     size_t total = 0;
 };
 
@@ -162,8 +162,10 @@ struct ehyb_plan {
     std::vector<int32_t> row_ell_len, row_er_len;  // [n], permuted rows
     // pieces of the wide residual slices (derived from er_meta): piece_start
     // [ner_slices+1] gives each slice's first piece (none for other slices),
-    // pieces [3*n_pieces] = (slice, first step, end step)
-    std::vector<int32_t> piece_start, pieces;
+    // piece_nwide [nparts] the number of wide slices, which lead each
+    // partition's residual slices, pieces [3*n_pieces] = (slice, first step,
+    // end step)
+    std::vector<int32_t> piece_start, piece_nwide, pieces;
     int32_t n_pieces = 0;
     int64_t ell_slots = 0, er_slots = 0;
     int64_t nnz_ell = 0, nnz_er = 0, n_er_rows = 0, nnz_halo = 0;

@@ -1,7 +1,9 @@
 """Fixed kernel sequence for hardware-counter runs (rocprofv3 --pmc).
 
 Runs the headline EHYB FP64 product (or, with ``--workload batched``, the
-batched product of 64 FP32 matrices x 8 right-hand sides) `--reps` times and
+batched product of 64 FP32 matrices x 8 right-hand sides; with ``--workload
+powerlaw``, the FP64 product of the 2.5e5-row power-law graph with hub rows,
+default plan: the hub-row pre-pass, then the product) `--reps` times and
 the copy probe on a buffer of known size `--reps` times, nothing else on the GPU, so that the
 per-dispatch FETCH_SIZE / WRITE_SIZE of each kernel can be read off and the
 EHYB counters scaled by what the same counters report for the copy of a known
@@ -21,7 +23,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "batched"])
+    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "batched", "powerlaw"])
     args = ap.parse_args()
     import torch
 
@@ -34,6 +36,15 @@ def main():
         A = matgen.config_matrix(HEADLINE["config"])
         x = matgen.uniform_vector(A.n_rows, HEADLINE["x_seed"])
         plan = Plan(A, **HEADLINE_PARAMS).upload(dev)
+        algo = plan.stats()["algorithmic_bytes"]
+        xp = torch.from_numpy(x[plan.perm()]).to(dev)
+        yp = torch.empty_like(xp)
+        run = lambda: plan.spmv(xp, yp)  # noqa: E731
+    elif args.workload == "powerlaw":
+        from paper_2204_06666_amd.workloads import POWERLAW
+        A = matgen.powerlaw(**POWERLAW["matgen"])
+        x = matgen.uniform_vector(A.n_rows, POWERLAW["x_seed"])
+        plan = Plan(A).upload(dev)
         algo = plan.stats()["algorithmic_bytes"]
         xp = torch.from_numpy(x[plan.perm()]).to(dev)
         yp = torch.empty_like(xp)

@@ -52,27 +52,49 @@ def kernel_source_hash():
 
 
 def trace_summary(trace_dir, warmup, steps, kernel=KERNEL, top=10):
+    """Kernel statistics, and the mean duration of dispatches warmup ..
+    warmup + steps - 1 of each summarised kernel ("|"-separated names), with
+    the number of dispatches of the first."""
     stats = list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_stats.csv")))))
     rows = list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_trace.csv")))))
-    ehyb = sorted((r for r in rows if kernel in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
-    dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in ehyb]
-    window = dur[warmup:warmup + steps]
-    return stats[:top], (statistics.mean(window) if window else None), len(ehyb)
+    means, count = {}, None
+    for name in kernel.split("|"):
+        ehyb = sorted((r for r in rows if name in r["Kernel_Name"]), key=lambda r: int(r["Start_Timestamp"]))
+        dur = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) for r in ehyb]
+        window = dur[warmup:warmup + steps]
+        means[name] = statistics.mean(window) if window else None
+        count = len(ehyb) if count is None else count
+    return stats[:top], means, count
 
 
 def pmc_values(pmc_dir, counter, kernel=KERNEL, scale=1024.0):
     """Mean per dispatch of `counter` for the EHYB kernel and for the copy
-    probe (FETCH_SIZE / WRITE_SIZE are KiB: scale 1024; request counts: 1)."""
+    probe (FETCH_SIZE / WRITE_SIZE are KiB: scale 1024; request counts: 1).
+    `kernel` may name several kernels separated by "|" that each run once
+    per product (the hub-row pre-pass and the product): "ehyb" is then the
+    sum of their means, the count per product."""
     rows = list(csv.DictReader(open(_one(os.path.join(pmc_dir, "**", "*counter_collection.csv")))))
-    out = {}
+    names = kernel.split("|")
+    per = {n: [] for n in names}
+    copy = []
     for r in rows:
         if r["Counter_Name"] != counter:
             continue
         name = r["Kernel_Name"]
-        key = "ehyb" if kernel in name else ("copy" if "probe_copy_kernel" in name else None)
-        if key:
-            out.setdefault(key, []).append(float(r["Counter_Value"]) * scale)
-    return {k: statistics.mean(v) for k, v in out.items()}
+        v = float(r["Counter_Value"]) * scale
+        if "probe_copy_kernel" in name:
+            copy.append(v)
+            continue
+        for n in names:
+            if n in name:
+                per[n].append(v)
+                break
+    out = {}
+    if all(per[n] for n in names):
+        out["ehyb"] = sum(statistics.mean(per[n]) for n in names)
+    if copy:
+        out["copy"] = statistics.mean(copy)
+    return out
 
 
 def request_bytes(rd_dir, wr_dir, kernel):
@@ -121,7 +143,8 @@ def main():
     args = ap.parse_args()
     kernel = args.kernel
 
-    stats, window_ns, n_disp = trace_summary(args.trace, args.warmup, args.steps, kernel)
+    stats, window_means, n_disp = trace_summary(args.trace, args.warmup, args.steps, kernel)
+    window_ns = sum(window_means.values())
     log = open(args.fetch_log).read()
     m = re.search(r"ehyb algorithmic_bytes=(\d+) copy_bytes_read=(\d+) copy_bytes_written=(\d+)", log)
     algo, copy_r, copy_w = (int(g) for g in m.groups())
@@ -151,9 +174,16 @@ def main():
         name = (name[5:] if name.startswith("void ") else name).split("(")[0][:60] or "(unnamed)"
         lines.append(f"| `{name}` | {s['Calls']} | {float(s['AverageNs']) / 1e3:.2f} | "
                      f"{float(s['MinNs']) / 1e3:.2f} | {float(s['MaxNs']) / 1e3:.2f} |")
-    lines += ["", f"Dispatches of `{kernel}` traced: {n_disp}. The benchmark's timed window is "
-                  f"dispatches {args.warmup}..{args.warmup + args.steps - 1} (after {args.warmup} "
-                  f"warm-up launches); their mean duration is **{window_ns / 1e3:.2f} us**."]
+    if len(window_means) == 1:
+        lines += ["", f"Dispatches of `{kernel}` traced: {n_disp}. The benchmark's timed window is "
+                      f"dispatches {args.warmup}..{args.warmup + args.steps - 1} (after {args.warmup} "
+                      f"warm-up launches); their mean duration is **{window_ns / 1e3:.2f} us**."]
+    else:
+        each = ", ".join(f"`{k}` {v / 1e3:.2f} us" for k, v in window_means.items())
+        lines += ["", f"One product is one dispatch of each of {len(window_means)} kernels ({n_disp} products "
+                      f"traced). Over products {args.warmup}..{args.warmup + args.steps - 1} (after "
+                      f"{args.warmup} warm-up products) their mean durations are {each}: "
+                      f"**{window_ns / 1e3:.2f} us** of kernel time per product."]
     if bench:
         lines.append(f"bench.py measured {bench['roofline']['launch_us']} us per launch with HIP "
                      f"events in the same run ({bench['value']} GFLOP/s).")

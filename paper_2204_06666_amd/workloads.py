@@ -30,6 +30,16 @@ HEADLINE_PARAMS = {
 # part and reads x from device memory.
 PAPER_SPLIT_PARAMS = dict(HEADLINE_PARAMS, halo_rows=-1, ell_width_cap=-1)
 
+# The larger power-law graph (Chung-Lu, hub rows of ~10^5 entries) of the
+# power-law benchmark, FP64, default plan.
+POWERLAW = {
+    "name": "powerlaw-2.5e5",
+    "workload": "Chung-Lu power-law graph, n=2.5e5, degree exponent 2.1, mean degree 40 (seed 7), "
+                "x ~U[-1,1] (seed 3), FP64, default plan",
+    "matgen": dict(n=250000, exponent=2.1, mean_deg=40, seed=7),
+    "x_seed": 3,
+}
+
 # the batched product (64 uneven FP32 matrices x 8 right-hand sides): plans
 # within half the LDS, so that two workgroups share a CU
 BATCHED_PARAMS = dict(n_rhs=8, lds_bytes=80 * 1024, halo_rows=0, rows_per_wave=64)
