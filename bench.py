@@ -499,10 +499,17 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+KNN_TRAFFIC = {"f64": "ehyb_spmv_f64_knnfem_traffic.json", "f32": "ehyb_spmv_f32_knnfem_traffic.json",
+               "bf16": "ehyb_spmv_bf16_knnfem_traffic.json"}
+
+
 def run_precision(args):
     """Unstructured-FEM matrix (mutual kNN, 3x3 blocks): FP64 values against
     FP32 and BF16 values with binary32 x and accumulation, each with its error
-    against the FP64 product of the original values (scipy's CSR product)."""
+    against the FP64 product of the original values (scipy's CSR product), its
+    roofline (algorithmic bytes over the HIP-event time per product) and the
+    committed rocprofv3 traffic of its kernel; the CPU oracle (FP64) on the
+    whole matrix as the CPU baseline."""
     import numpy as np
     import torch
 
@@ -537,6 +544,12 @@ def run_precision(args):
                      "algorithmic_bytes": st["algorithmic_bytes"],
                      "algorithmic_GBps": round(st["algorithmic_bytes"] / kern / 1e9, 1),
                      "pct_of_8TBps": round(100 * st["algorithmic_bytes"] / kern / 8e12, 2),
+                     "roofline": {"bound": "hbm", "achieved": round(st["algorithmic_bytes"] / kern / 1e9, 1),
+                                  "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                                  "frac": round(st["algorithmic_bytes"] / kern / 1e9 / PEAK_HBM_GBPS, 4),
+                                  "traffic": load_traffic(kernel_source_hash(), KNN_TRAFFIC[name])
+                                  if name in KNN_TRAFFIC else None,
+                                  "launch_us": round(kern * 1e6, 2)},
                      "max_row_scaled_error_vs_fp64": float(e.max()),
                      "normwise_rel_error_vs_fp64": float(np.linalg.norm(y - y64) / np.linalg.norm(y64)),
                      "nparts": st["nparts"], "nnz_er": st["nnz_er"], "nnz_halo": st["nnz_halo"],
@@ -550,6 +563,12 @@ def run_precision(args):
             del rp, ci, v
         log(f"{name}: {res[name]}")
         del plan, xt, yt
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("CPU oracle baseline")
+        cpu = cpu_oracle_baseline(oracle, A, x, flops, "the whole kNN-FEM matrix (FP64)")
+    r64 = res["f64"]["roofline"]
     out = {
         "metric": METRIC, "value": res["f64"]["GFLOPs"], "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(res["f64"]["us_per_step"] / 1e3, 5),
@@ -557,6 +576,9 @@ def run_precision(args):
         "data": "synthetic",
         "config": {"workload": f"mutual-kNN FEM stand-in, {int(1_000_000 * args.scale)} points ~U[0,1]^3, "
                                f"k ~ U{{12..40}}, 3x3 blocks (seeds 3000-3003)", "n": n, "nnz": nnz},
+        "roofline": dict(r64, kernel="ehyb_spmv_kernel<EHYB_F64, L=1, streaming loads>",
+                         algorithmic_bytes=res["f64"]["algorithmic_bytes"]),
+        "cpu_baseline": cpu,
         "precision": res,
     }
     print(json.dumps(out), flush=True)

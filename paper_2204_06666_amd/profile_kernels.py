@@ -3,13 +3,20 @@
 Runs the headline EHYB FP64 product (or, with ``--workload batched``, the
 batched product of 64 FP32 matrices x 8 right-hand sides; with ``--workload
 powerlaw``, the FP64 product of the 2.5e5-row power-law graph with hub rows,
-default plan: the hub-row pre-pass, then the product) `--reps` times and
+default plan: the hub-row pre-pass, then the product; with ``--workload
+knnfem``, the products of the 3e6-row kNN-FEM matrix with FP64, FP32 and
+BF16 values, one after the other) `--reps` times and
 the copy probe on a buffer of known size `--reps` times, nothing else on the GPU, so that the
 per-dispatch FETCH_SIZE / WRITE_SIZE of each kernel can be read off and the
 EHYB counters scaled by what the same counters report for the copy of a known
-number of bytes.
+number of bytes.  One line per product kind is printed:
+``ehyb[TAG] algorithmic_bytes=... copy_bytes_read=... copy_bytes_written=...``.
 
     rocprofv3 --pmc FETCH_SIZE -d OUT -o fetch -- python3 paper_2204_06666_amd/profile_kernels.py
+
+``--cache-dir DIR`` keeps the generated kNN-FEM matrix and its plans between
+the counter passes of one session (the matrix takes about a minute to
+generate).
 """
 import argparse
 import os
@@ -23,7 +30,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "batched", "powerlaw"])
+    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "batched", "powerlaw", "knnfem"])
+    ap.add_argument("--cache-dir", default=None, help="knnfem: keep the matrix and plans here between runs")
     args = ap.parse_args()
     import torch
 
@@ -32,6 +40,7 @@ def main():
     from paper_2204_06666_amd.workloads import HEADLINE, HEADLINE_PARAMS
 
     dev = torch.device("cuda:0")
+    tags = ["ehyb"]
     if args.workload == "stencil27":
         A = matgen.config_matrix(HEADLINE["config"])
         x = matgen.uniform_vector(A.n_rows, HEADLINE["x_seed"])
@@ -49,6 +58,24 @@ def main():
         xp = torch.from_numpy(x[plan.perm()]).to(dev)
         yp = torch.empty_like(xp)
         run = lambda: plan.spmv(xp, yp)  # noqa: E731
+    elif args.workload == "knnfem":
+        import numpy as np
+
+        from paper_2204_06666_amd import EHYB_BF16, EHYB_F32, EHYB_F64
+        A = _knn_matrix(args.cache_dir)
+        x = matgen.uniform_vector(A.n_rows, matgen.CONFIG_SEEDS[3] + 2)
+        tags, algo, runs = [], [], []
+        for tag, dt in (("f64", EHYB_F64), ("f32", EHYB_F32), ("bf16", EHYB_BF16)):
+            plan = _cached_plan(A, dt, args.cache_dir, tag).upload(dev)
+            xt = torch.from_numpy(x[plan.perm()].astype(np.float64 if dt == EHYB_F64 else np.float32)).to(dev)
+            runs.append((plan, xt, torch.empty_like(xt)))
+            tags.append(f"ehyb[{tag}]")
+            algo.append(plan.stats()["algorithmic_bytes"])
+
+        def run():
+            for p, xt, yt in runs:
+                for _ in range(args.reps):
+                    p.spmv(xt, yt)
     else:
         from paper_2204_06666_amd import EHYB_F32, Batch
         from paper_2204_06666_amd.workloads import BATCHED_PARAMS, batched_tuned
@@ -65,14 +92,46 @@ def main():
     src = torch.ones((args.copy_mib << 20) // 4, dtype=torch.float32, device=dev)
     dst = torch.empty_like(src)
     torch.cuda.synchronize()
-    for _ in range(args.reps):
-        run()
+    if args.workload == "knnfem":
+        run()  # each product kind `reps` times in a row
+    else:
+        for _ in range(args.reps):
+            run()
+        algo = [algo]
     torch.cuda.synchronize()
     for _ in range(args.reps):
         probe_copy(src, dst)
     torch.cuda.synchronize()
-    print(f"ehyb algorithmic_bytes={algo} copy_bytes_read={src.numel() * 4} "
-          f"copy_bytes_written={dst.numel() * 4} reps={args.reps}", flush=True)
+    for tag, a in zip(tags, algo):
+        print(f"{tag} algorithmic_bytes={a} copy_bytes_read={src.numel() * 4} "
+              f"copy_bytes_written={dst.numel() * 4} reps={args.reps}", flush=True)
+
+
+def _knn_matrix(cache_dir):
+    """The 3e6-row kNN-FEM matrix, generated or read back from `cache_dir`."""
+    import numpy as np
+
+    import matgen
+    path = os.path.join(cache_dir, "knnfem.npz") if cache_dir else None
+    if path and os.path.exists(path):
+        z = np.load(path)
+        return matgen.Csr(int(z["n"]), int(z["n"]), z["row_ptr"], z["col"], z["val"])
+    A = matgen.config_matrix(3)
+    if path:
+        os.makedirs(cache_dir, exist_ok=True)
+        np.savez(path, n=A.n_rows, row_ptr=A.row_ptr, col=A.col, val=A.val)
+    return A
+
+
+def _cached_plan(A, dt, cache_dir, tag):
+    from paper_2204_06666_amd import Plan
+    path = os.path.join(cache_dir, f"knnfem_{tag}.plan") if cache_dir else None
+    if path and os.path.exists(path):
+        return Plan.load(path)
+    plan = Plan(A, value_dtype=dt)
+    if path:
+        plan.save(path)
+    return plan
 
 
 if __name__ == "__main__":

@@ -140,13 +140,15 @@ def main():
     ap.add_argument("--kernel", default=KERNEL, help="substring of the kernel name to summarise")
     ap.add_argument("--title", default="EHYB FP64 SpMV, 27-point stencil 100^3 (1e6 rows, 26,463,592 nnz)")
     ap.add_argument("--workload-name", default="stencil27-100^3")
+    ap.add_argument("--log-tag", default="ehyb", help="product kind in the fetch log (ehyb, ehyb[f32], ...)")
     args = ap.parse_args()
     kernel = args.kernel
 
     stats, window_means, n_disp = trace_summary(args.trace, args.warmup, args.steps, kernel)
     window_ns = sum(window_means.values())
     log = open(args.fetch_log).read()
-    m = re.search(r"ehyb algorithmic_bytes=(\d+) copy_bytes_read=(\d+) copy_bytes_written=(\d+)", log)
+    m = re.search(re.escape(args.log_tag) + r" algorithmic_bytes=(\d+) copy_bytes_read=(\d+) copy_bytes_written=(\d+)",
+                  log)
     algo, copy_r, copy_w = (int(g) for g in m.groups())
     fetch = pmc_values(args.fetch, "FETCH_SIZE", kernel)
     write = pmc_values(args.write, "WRITE_SIZE", kernel)
