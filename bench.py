@@ -830,8 +830,7 @@ def run_predictor(args):
 
     import matgen
     from paper_2204_06666_amd import EHYB_F32, Plan, features
-    from paper_2204_06666_amd.autotune import time_spmv
-    from paper_2204_06666_amd.predictor import lds_max_rows, width_cap
+    from paper_2204_06666_amd.autotune import plan_for_point, time_spmv
     from paper_2204_06666_amd.train_predictor import Predictor, best, evaluate, load_sweeps, train
 
     data = os.path.join(ROOT, "paper_2204_06666_amd", "data")
@@ -856,18 +855,10 @@ def run_predictor(args):
         f = features(A)
         if not np.allclose(f, rec["features"], rtol=1e-5, atol=1e-6):
             raise SystemExit(f"features of matrix {rec['i']} differ from the recorded sweep")
-        lens = np.diff(A.row_ptr)
         x = torch.from_numpy(matgen.uniform_vector(A.n_rows, 7).astype(np.float32)).to("cuda:0")
         y = torch.empty_like(x)
-
-        def plan_for(point):
-            s, q, r = point
-            base = Plan(A, value_dtype=EHYB_F32, slice_rows=s or lds_max_rows())
-            return Plan(A, value_dtype=EHYB_F32, partition=base.partition(), ell_width_cap=width_cap(lens, q),
-                        rows_per_wave=r).upload("cuda:0")
-
-        tp = time_spmv(torch, plan_for(pt), x, y, 50, 5)
-        tb = time_spmv(torch, plan_for(best(rec)[0]), x, y, 50, 5)
+        tp = time_spmv(torch, plan_for_point(A, pt).upload("cuda:0"), x, y, 50, 5)
+        tb = time_spmv(torch, plan_for_point(A, best(rec)[0]).upload("cuda:0"), x, y, 50, 5)
         te1 = time_spmv(torch, Plan(A, value_dtype=EHYB_F32).upload("cuda:0"), x, y, 50, 5)
         live.append({"i": rec["i"], "desc": desc, "pred_us": round(tp * 1e6, 2), "best_us": round(tb * 1e6, 2),
                      "eq1_us": round(te1 * 1e6, 2)})

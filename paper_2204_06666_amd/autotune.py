@@ -81,6 +81,16 @@ def sweep_matrix(A, device="cuda:0", launches: int = 20, rounds: int = 3) -> dic
             "times_us": times, "eq1": eq1, "preprocess_s": round(t_pre, 2)}
 
 
+def plan_for_point(A, point) -> Plan:
+    """The FP32 plan of grid point (partition size, width quantile, rows per
+    wave), built as the sweep builds it: a partition of that size, then the
+    encoding with that ELL cap and lane count."""
+    s, q, r = point
+    base = Plan(A, value_dtype=EHYB_F32, slice_rows=s or lds_max_rows())
+    return Plan(A, value_dtype=EHYB_F32, partition=base.partition(), ell_width_cap=width_cap(np.diff(A.row_ptr), q),
+                rows_per_wave=r)
+
+
 def grid_points(rec: dict):
     """[(slice_rows, width_q, rows_per_wave, time_us)] of a sweep record."""
     out = []

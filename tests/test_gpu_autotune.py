@@ -4,9 +4,9 @@ import pytest
 
 import matgen
 from paper_2204_06666_amd import EHYB_F32, Plan, features
-from paper_2204_06666_amd.autotune import best_point, grid_points, sweep_matrix
+from paper_2204_06666_amd.autotune import best_point, grid_points, plan_for_point, sweep_matrix, time_spmv
 from paper_2204_06666_amd.predictor import ROWS_PER_WAVE, SLICE_ROWS, WIDTH_QUANTILES, width_cap
-from paper_2204_06666_amd.train_predictor import evaluate, train
+from paper_2204_06666_amd.train_predictor import Predictor, best, evaluate, load_sweeps, train
 
 pytestmark = pytest.mark.gpu
 
@@ -64,3 +64,38 @@ def test_batch_tuner_on_a_small_batch():
         n *= len(v)
     assert len(res["points"]) == n and res["best_us"] == min(t for _, t in res["points"])
     assert set(res["best"]) == set(BATCH_GRID)
+
+
+def test_committed_predictor_live_on_held_out_matrices():
+    """Every held-out matrix of the committed sweep with at most 30,000 rows
+    (33 matrices), regenerated from its seed: the committed network predicts
+    its grid point on the device, and the predicted plan, the Eq. 1 default
+    plan and the plan of the recorded best grid point are built and timed
+    now.  Over these matrices the predicted plans are within 1.10x of the best
+    point and faster than the Eq. 1 default (geometric means)."""
+    import os
+
+    import torch
+    data = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2204_06666_amd", "data")
+    model = Predictor.load(os.path.join(data, "predictor_fp32.json"))
+    import json
+    n_train = json.load(open(os.path.join(data, "predictor_fp32.json")))["meta"]["n_train"]
+    held = [r for r in load_sweeps([os.path.join(data, "tuning_sweep.jsonl")]) if r["i"] >= n_train and r["n"] <= 30_000]
+    assert len(held) >= 8
+    r_best, r_eq1 = [], []
+    for rec in held:
+        _, A = matgen.tuning_matrix(rec["i"], n_hi=250_000)
+        assert (A.n_rows, A.nnz) == (rec["n"], rec["nnz"]), rec["i"]
+        pt = model.predict([features(A)])[0]
+        x = torch.from_numpy(matgen.uniform_vector(A.n_rows, 7).astype(np.float32)).to("cuda:0")
+        y = torch.empty_like(x)
+        tp = time_spmv(torch, plan_for_point(A, pt).upload("cuda:0"), x, y, 30, 3)
+        tb = time_spmv(torch, plan_for_point(A, best(rec)[0]).upload("cuda:0"), x, y, 30, 3)
+        t1 = time_spmv(torch, Plan(A, value_dtype=EHYB_F32).upload("cuda:0"), x, y, 30, 3)
+        r_best.append(tp / min(tb, tp))
+        r_eq1.append(t1 / tp)
+    gm = lambda a: float(np.exp(np.mean(np.log(a))))  # noqa: E731
+    print(f"[predictor live] {len(held)} held-out matrices: predicted / best {gm(r_best):.3f}, "
+          f"Eq. 1 / predicted {gm(r_eq1):.3f}", flush=True)
+    assert gm(r_best) <= 1.10
+    assert gm(r_eq1) > 1.0
