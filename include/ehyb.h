@@ -260,10 +260,13 @@ typedef struct ehyb_plan ehyb_plan;
 EHYB_API ehyb_status ehyb_preprocess(const ehyb_csr_host *A, const ehyb_params *params,
                             ehyb_plan **out);
 
-/* Statistics of a plan. */
+/* Statistics of a plan, all in one struct (sizes, part sizes, bytes per
+ * product, preprocessing time by phase), filled by one call. */
 EHYB_API ehyb_status ehyb_plan_stats_get(const ehyb_plan *plan, ehyb_plan_stats *out);
 
-/* Views of a plan's host arrays (see ehyb_plan_arrays). */
+/* Views of a plan's host arrays (see ehyb_plan_arrays), valid while the
+ * plan lives.  The row permutation is one of them (`perm`: row i of the plan
+ * is row perm[i] of A); there is no separate call for it. */
 EHYB_API ehyb_status ehyb_plan_arrays_get(const ehyb_plan *plan, ehyb_plan_arrays *out);
 
 /* Decode the plan back to CSR of P A P^T (B[i][j] = A[perm[i]][perm[j]]),
