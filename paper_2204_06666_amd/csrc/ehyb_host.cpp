@@ -208,6 +208,46 @@ Graph build_graph(const ehyb_csr_host* A) {
     return g;
 }
 
+// Work-weighted partition balance.  The paper sizes partitions by rows
+// (Eq. 1); on power-law graphs the rows many times longer than the mean fall
+// into a few partitions (the partitioner keeps densely linked hubs together),
+// whose workgroups then set the time of the launch.  A row of at least twice
+// the mean length weighs its ELL-eligible entries (up to the width cap; 0 =
+// no cap) in units of the mean length, at most min(64, row_cap / 8); every
+// other row weighs 1, so matrices without such rows are partitioned exactly
+// as by rows.  The partition count stays Eq. 1's.  The returned weight cap is
+// the mean weight per partition plus the allowed imbalance, never below the
+// row cap and never above the LDS row limit: a partition's rows, each
+// weighing at least 1, always fit its LDS.  Where the LDS limit leaves no room
+// for the weights, rows are balanced as without them.
+int64_t weigh_long_rows(Graph& g, const ehyb_csr_host* A, int64_t width_cap, int32_t nparts, int64_t row_cap,
+                        int64_t max_rows, int32_t imbalance_pct) {
+    const int64_t n = g.n;
+    if (n == 0 || A->nnz == 0 || nparts < 1) return row_cap;
+    const double mean = (double)A->nnz / (double)n;
+    const double wmax = (double)std::max<int64_t>(1, std::min<int64_t>(64, row_cap / 8));
+    int64_t sumw = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        const int64_t len = A->row_ptr[v + 1] - A->row_ptr[v];
+        int32_t w = 1;
+        if ((double)len >= 2.0 * mean) {
+            const int64_t e = width_cap > 0 ? std::min<int64_t>(len, width_cap) : len;
+            w = (int32_t)std::min(wmax, std::max(1.0, std::floor((double)e / mean)));
+        }
+        g.vw[v] = w;
+        sumw += w;
+    }
+    const int64_t wcap = std::min<int64_t>(max_rows, std::max<int64_t>(
+        row_cap, (sumw + nparts - 1) / nparts * (100 + imbalance_pct) / 100));
+    if (wcap * nparts < sumw) {
+        // partitions already at the LDS row limit: the weights do not fit,
+        // balance rows as before
+        std::fill(g.vw.begin(), g.vw.end(), 1);
+        return row_cap;
+    }
+    return wcap;
+}
+
 }  // namespace
 
 ehyb_status fail(ehyb_status st, const std::string& msg) {
@@ -796,7 +836,8 @@ ehyb_status preprocess_impl(const ehyb_csr_host* A, const ehyb_params* params, c
             Graph g = build_graph(A);
             P->t_graph = now_s() - t0;
             t0 = now_s();
-            Error pe = partition_multilevel(g, nparts_req, cap, prm.seed, part, nparts);
+            const int64_t wcap = weigh_long_rows(g, A, prm.ell_width_cap, nparts_req, cap, max_rows, prm.imbalance_pct);
+            Error pe = partition_multilevel(g, nparts_req, wcap, prm.seed, part, nparts);
             if (!pe.ok()) return fail(pe.status, pe.msg);
             P->t_partition = now_s() - t0;
         }

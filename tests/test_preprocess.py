@@ -409,3 +409,28 @@ def test_wide_slice_pieces(tmp_path):
     P.save(f)
     assert Plan.load(f).stats()["n_er_pieces"] == st["n_er_pieces"]
     assert Plan(matgen.stencil3d(12, perm_seed=1, val_seed=2)).stats()["n_er_pieces"] == 0
+
+
+@pytest.mark.parametrize("seed,n,slice_rows", [(3, 20000, 1000), (7, 60000, 2000), (11, 40000, 0)])
+def test_partitions_balance_work_on_power_law(seed, n, slice_rows):
+    """Rows at least twice the mean length weigh their ELL-eligible entries
+    in the partition balance: on power-law graphs, whose hub rows the
+    partitioner keeps together, no partition streams much more ELL work than
+    the median one (by rows alone the heaviest held about 4x the median)."""
+    A = matgen.powerlaw(n, exponent=2.1, mean_deg=20, seed=seed)
+    P = Plan(A, slice_rows=slice_rows)
+    _full_check(A, P)
+    ar = P.arrays()
+    ss, meta = ar["slice_start"], ar["ell_meta"]
+    ell = np.array([int((meta[ss[p]:ss[p + 1], 1].astype(np.int64) & 0xFFFF).sum()) for p in range(len(ss) - 1)])
+    assert ell.max() <= 1.6 * np.median(ell), (ell.max(), np.median(ell))
+
+
+def test_work_weights_fall_back_at_the_lds_limit():
+    """Partitions already at the LDS row limit leave no room for the weights:
+    the plan is built balancing rows, within the limit."""
+    A = matgen.powerlaw(30000, exponent=2.1, mean_deg=20, seed=5)
+    lim = (160 * 1024 - 64) // 16
+    P = Plan(A, slice_rows=lim, imbalance_pct=0)
+    _full_check(A, P)
+    assert P.stats()["max_part_rows"] <= lim
