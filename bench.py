@@ -406,7 +406,11 @@ def main():
             "after_flush_in_graph_us": time_cold_graph(torch, lambda st: plan.spmv(xp, yp, stream=st), flush)}
     plan.set_load_mode(EHYB_LOAD_AUTO)
     cold_csr = time_cold(torch, lambda: csr_spmv(rp, ci, cv, xo, yo, best_l), flush, 30)
-    del fbuf
+    # a plain streaming read of the product's algorithmic bytes, timed the same
+    # way: what HBM delivers cold to a launch of this size
+    pbuf = torch.ones(algo // 64 * 64, dtype=torch.uint8, device=dev)
+    cold_read = time_cold_graph(torch, lambda st: probe_read(pbuf, sink, stream=st), flush)
+    del fbuf, pbuf
     # the cold headline: streaming loads (a product that reuses nothing from the
     # caches), the incremental time in a stream after other work
     cold_s = cold["stream"]["after_flush_in_graph_us"]
@@ -460,6 +464,8 @@ def main():
                      "cold": {"us": round(cold_s * 1e6, 2), "achieved": round(algo / cold_s / 1e9, 1),
                               "frac": round(algo / cold_s / 1e9 / PEAK_HBM_GBPS, 4),
                               "pct_of_measured_hbm": round(100 * algo / cold_s / 1e9 / hbm_meas, 2),
+                              "same_size_read_cold_us": round(cold_read * 1e6, 2),
+                              "pct_of_same_size_cold_read": round(100 * cold_read / cold_s, 2),
                               "load_mode": "stream",
                               "protocol": "L2 and Infinity Cache flushed (1 GiB read with cache-allocating "
                                           "loads) before each product; HIP graph of 20 (flush, product) pairs "
