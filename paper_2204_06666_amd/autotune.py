@@ -91,6 +91,13 @@ def plan_for_point(A, point) -> Plan:
                 rows_per_wave=r)
 
 
+def choose_plan(predictor, A, device="cuda:0") -> Plan:
+    """The FP32 plan of the point the predictor chooses for A, or the Eq. 1
+    default plan where A lies outside the predictor's training range."""
+    pt = predictor.choose([features(A)], [A.n_rows], device)[0]
+    return plan_for_point(A, pt) if pt is not None else Plan(A, value_dtype=EHYB_F32)
+
+
 def grid_points(rec: dict):
     """[(slice_rows, width_q, rows_per_wave, time_us)] of a sweep record."""
     out = []
@@ -157,6 +164,8 @@ def main(argv=None):
     ap.add_argument("--n-lo", type=int, default=10_000)
     ap.add_argument("--n-hi", type=int, default=250_000)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--indices", type=int, nargs="*", default=None,
+                    help="sweep these matrix indices instead of --start/--count")
     ap.add_argument("--batch", action="store_true",
                     help="tune the batched product of the 64-matrix batch instead (writes JSON)")
     args = ap.parse_args(argv)
@@ -167,7 +176,7 @@ def main(argv=None):
         print(f"[autotune] batch best {res['best']} {res['best_us']} us", flush=True)
         return 0
     with open(args.out, "a") as f:
-        for i in range(args.start, args.start + args.count):
+        for i in (args.indices if args.indices else range(args.start, args.start + args.count)):
             t0 = time.perf_counter()
             desc, A = matgen.tuning_matrix(i, n_lo=args.n_lo, n_hi=args.n_hi)
             t_gen = time.perf_counter() - t0

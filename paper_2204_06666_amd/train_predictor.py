@@ -86,12 +86,15 @@ def evaluate(recs, points):
 
 
 class Predictor:
-    """Network + feature normalisation; predicts grid points from features."""
+    """Network + feature normalisation; predicts grid points from features.
+    `n_range` is the (smallest, largest) row count of the training matrices:
+    ``choose`` trusts the network only inside it."""
 
-    def __init__(self, params, mean, std):
+    def __init__(self, params, mean, std, n_range=None):
         self.params = np.asarray(params, dtype=np.float32)
         self.mean = np.asarray(mean, dtype=np.float64)
         self.std = np.asarray(std, dtype=np.float64)
+        self.n_range = tuple(n_range) if n_range else None
 
     def normalise(self, F):
         return ((transform(np.atleast_2d(F)) - self.mean) / self.std).astype(np.float32)
@@ -102,14 +105,26 @@ class Predictor:
         Y = Mlp(self.params, device=device).forward(X).cpu().numpy()
         return [decode_output(y) for y in Y]
 
+    def choose(self, F, n_rows, device="cuda:0"):
+        """Grid points for matrices with features F and row counts n_rows;
+        None (use the Eq. 1 default) where a matrix lies outside the training
+        matrices' row-count range: measured on matrices of 2.7e5-9.7e5 rows,
+        a network trained on 1e4-2.5e5 rows chose points 1.21x the grid's best
+        while the default took 0.92x."""
+        pts = self.predict(F, device)
+        if self.n_range is None:
+            return pts
+        lo, hi = self.n_range
+        return [p if lo <= n <= hi else None for p, n in zip(pts, np.atleast_1d(n_rows))]
+
     def save(self, path, meta=None):
         json.dump({"params": self.params.tolist(), "mean": self.mean.tolist(), "std": self.std.tolist(),
-                   "meta": meta or {}}, open(path, "w"))
+                   "n_range": list(self.n_range) if self.n_range else None, "meta": meta or {}}, open(path, "w"))
 
     @classmethod
     def load(cls, path):
         d = json.load(open(path))
-        return cls(d["params"], d["mean"], d["std"])
+        return cls(d["params"], d["mean"], d["std"], d.get("n_range"))
 
 
 def train(recs_train, epochs=400, batch=64, lr=2e-3, seed=0, near=0.0, device="cuda:0"):
@@ -122,7 +137,9 @@ def train(recs_train, epochs=400, batch=64, lr=2e-3, seed=0, near=0.0, device="c
     T = np.stack([target(r, near) for r in recs_train]).astype(np.float32)
     net = Mlp(seed=seed, device=device)
     hist = net.fit(torch.from_numpy(X).to(device), torch.from_numpy(T).to(device), epochs, batch, lr, seed)
-    return Predictor(net.numpy_params(), mean, std), hist
+    n_range = ((min(r["n"] for r in recs_train), max(r["n"] for r in recs_train))
+               if all("n" in r for r in recs_train) else None)
+    return Predictor(net.numpy_params(), mean, std, n_range), hist
 
 
 def main(argv=None):

@@ -99,3 +99,17 @@ def test_committed_predictor_live_on_held_out_matrices():
           f"Eq. 1 / predicted {gm(r_eq1):.3f}", flush=True)
     assert gm(r_best) <= 1.10
     assert gm(r_eq1) > 1.0
+
+
+def test_choose_plan_uses_the_default_outside_the_training_range():
+    import os
+    data = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2204_06666_amd", "data")
+    from paper_2204_06666_amd.autotune import choose_plan
+    model = Predictor.load(os.path.join(data, "predictor_fp32.json"))
+    big = matgen.stencil3d(70, perm_seed=3)                      # 343,000 rows: above the range
+    assert big.n_rows > model.n_range[1]
+    assert choose_plan(model, big).stats()["slice_rows"] == Plan(big, value_dtype=EHYB_F32).stats()["slice_rows"]
+    small = matgen.stencil3d(30, perm_seed=3)                    # 27,000 rows: inside it
+    pt = model.choose([features(small)], [small.n_rows])[0]
+    assert pt is not None
+    assert choose_plan(model, small).stats()["rows_per_slice"] == pt[2]

@@ -70,3 +70,30 @@ def test_recorded_result_meets_the_targets():
     again = evaluate(te, [decode_output(y) for y in Y])
     assert abs(again["geomean_pred_over_best"] - res["geomean_pred_over_best"]) <= 0.01
     assert abs(again["geomean_eq1_over_pred"] - res["geomean_eq1_over_pred"]) <= 0.02
+
+
+PROBE = os.path.join(DATA, "tuning_sweep_large_probe.jsonl")
+
+
+def test_large_matrix_probe_and_the_range_guard():
+    """12 matrices of 2.7e5-9.7e5 rows swept over the full grid: all lie above
+    the committed network's training range, where its points are far from the
+    best (checked here with the FP64 reference network) and the Eq. 1 default
+    is within 10% of the grid's best (geomean), so Predictor.choose falls back
+    to the default for them."""
+    from oracle import mlp
+    from paper_2204_06666_amd.predictor import decode_output
+    from paper_2204_06666_amd.train_predictor import Predictor, evaluate
+    probe = load_sweeps([PROBE])
+    assert len(probe) == 12
+    pred = Predictor.load(MODEL)
+    lo, hi = pred.n_range
+    assert all(r["n"] > hi for r in probe)
+    Y, _ = mlp.forward(pred.params.astype(np.float64), pred.normalise([r["features"] for r in probe]).astype(np.float64))
+    res = evaluate(probe, [decode_output(y) for y in Y])
+    assert res["geomean_pred_over_best"] > 1.10
+    assert res["geomean_eq1_over_best"] <= 1.10
+    # the guard: points outside the range become None (the Eq. 1 default)
+    pred.predict = lambda F, device=None: [(256, None, 64)] * len(np.atleast_2d(F))
+    out = pred.choose([r["features"] for r in probe[:2]] + [probe[0]["features"]], [r["n"] for r in probe[:2]] + [lo])
+    assert out == [None, None, (256, None, 64)]
