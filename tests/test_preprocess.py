@@ -434,3 +434,23 @@ def test_work_weights_fall_back_at_the_lds_limit():
     P = Plan(A, slice_rows=lim, imbalance_pct=0)
     _full_check(A, P)
     assert P.stats()["max_part_rows"] <= lim
+
+
+def test_ell_slices_are_placed_round_by_round():
+    """ELL slot ranges follow the documented placement: queue positions 0-15
+    of every partition in partition order, then positions 16-31, and so on,
+    back to back."""
+    A = matgen.stencil3d(30, perm_seed=4, val_seed=5)
+    P = Plan(A, slice_rows=1500)
+    ar = P.arrays()
+    ss, meta = ar["slice_start"], ar["ell_meta"]
+    keys, offs, ends = [], [], []
+    for p in range(len(ss) - 1):
+        for q, s in enumerate(range(ss[p], ss[p + 1])):
+            keys.append((q // 16, p, q))
+            offs.append(int(meta[s, 0]))
+            ends.append(int(meta[s, 0]) + int(meta[s, 1] & 0xFFFF) * 64)
+    order = sorted(range(len(keys)), key=lambda k: keys[k])
+    assert offs[order[0]] == 0
+    assert all(offs[b] == ends[a] for a, b in zip(order, order[1:]))
+    assert max(max(ss[p + 1] - ss[p] for p in range(len(ss) - 1)), 0) > 16   # several rounds
