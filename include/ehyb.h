@@ -168,7 +168,7 @@ typedef struct {
     int32_t n_rhs;            /* right-hand sides the plan is sized for */
     int32_t n_er_wide;        /* wide residual slices (one long row, 64 lanes) */
     int32_t ell_width_cap;    /* ELL width cap in effect, 0 = none */
-    int32_t n_er_pieces;      /* pieces of at most 16 steps the wide residual
+    int32_t n_er_pieces;      /* pieces of at most 8 steps the wide residual
                                  slices are summed in by ehyb_spmv (0 = no
                                  wide slices) */
     double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */

@@ -131,7 +131,7 @@ def test_acc64_keeps_long_rows_accurate(rpw):
     binary32 rounding of the exact product of the stored values and x (error
     at most 2^-24 of sum |a_q x_q|); binary32 accumulation is measurably worse
     (by less than a plain running sum would be: the residual part of these
-    rows is summed in pieces of at most 1024 entries, which blocks the
+    rows is summed in pieces of at most 512 entries, which blocks the
     accumulation)."""
     g = matgen.rng(77)
     n = 2000

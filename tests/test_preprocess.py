@@ -393,7 +393,7 @@ def test_acc64_plans_size_lds_for_8_byte_accumulators():
 
 
 def test_wide_slice_pieces(tmp_path):
-    """ehyb_spmv sums each wide residual slice in pieces of at most 16 steps:
+    """ehyb_spmv sums each wide residual slice in pieces of at most 8 steps:
     their number follows from the slices' step counts, survives a plan file,
     and is zero for a plan without wide slices."""
     A = matgen.powerlaw(20000, exponent=2.2, mean_deg=20, seed=8)
@@ -403,7 +403,7 @@ def test_wide_slice_pieces(tmp_path):
     wide = (m[:, 1] >> 31) == 1
     steps = m[:, 1] & 0x7FFFFFFF
     assert st["n_er_wide"] == int(wide.sum()) > 0
-    assert st["n_er_pieces"] == int((-(-steps[wide] // 16)).sum())
+    assert st["n_er_pieces"] == int((-(-steps[wide] // 8)).sum())
     assert st["n_er_pieces"] > st["n_er_wide"]
     f = str(tmp_path / "p.bin")
     P.save(f)
