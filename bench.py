@@ -804,6 +804,7 @@ def run_powerlaw(args):
         res.append(row)
         last = (A, x)
     big = res[-1]["f64"]
+    batched = time_powerlaw_batch(args, torch, dev)
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -821,8 +822,50 @@ def run_powerlaw(args):
                         "kernel": "er_pieces_kernel<EHYB_F64> + ehyb_spmv_kernel<EHYB_F64, L=1, plain loads> "
                                   "(one product)",
                         "algorithmic_bytes": big["algorithmic_bytes"], "launch_us": big["us"]},
-           "cpu_baseline": cpu, "matrices": res}
+           "cpu_baseline": cpu, "matrices": res, "batched": batched}
     print(json.dumps(out), flush=True)
+
+
+def time_powerlaw_batch(args, torch, dev):
+    """The batched product over 12 power-law graphs (hub rows summed in pieces
+    over the whole device, for all graphs in one launch before the product):
+    FP32 x 8 right-hand sides and FP64 x 1, each graph checked against
+    scipy's FP64 product of the stored values."""
+    import numpy as np
+
+    import matgen
+    from paper_2204_06666_amd import EHYB_F32, EHYB_F64, Batch, Plan
+    from paper_2204_06666_amd.workloads import POWERLAW_BATCH, powerlaw_batch
+
+    log("generating the power-law batch")
+    mats = powerlaw_batch()
+    out = {"workload": f"{POWERLAW_BATCH['count']} Chung-Lu graphs, n log-uniform in [2e4, 2.5e5], exponent "
+                       "U[2.1, 2.5], mean degree U[10, 40]",
+           "n": int(sum(A.n_rows for A in mats)), "nnz": int(sum(A.nnz for A in mats))}
+    for name, dt, n_rhs, prm in (("f32x8", EHYB_F32, 8, dict(lds_bytes=80 * 1024, halo_rows=0)),
+                                 ("f64x1", EHYB_F64, 1, {})):
+        plans = [Plan(A, value_dtype=dt, n_rhs=n_rhs, rows_per_wave=64, **prm).upload(dev) for A in mats]
+        batch = Batch(plans, n_rhs, dev)
+        g = matgen.rng(11)
+        X = [g.uniform(-1, 1, (A.n_rows, n_rhs)) for A in mats]
+        tdt = torch.float64 if dt == EHYB_F64 else torch.float32
+        Xd = [torch.from_numpy(x[p.perm()]).to(dev, tdt).contiguous() for x, p in zip(X, plans)]
+        Yd = [torch.empty_like(v) for v in Xd]
+        wall, _ = time_launches(torch, lambda: batch.spmm(Xd, Yd), args.steps, args.warmup)
+        err = 0.0
+        for A, p, x, y in zip(mats, plans, X, Yd):
+            xq = x if dt == EHYB_F64 else x.astype(np.float32).astype(np.float64)
+            val = A.val if dt == EHYB_F64 else A.val.astype(np.float32).astype(np.float64)
+            ref, s = fp64_products(A.row_ptr, A.col, val, xq)
+            Y = np.empty((A.n_rows, n_rhs))
+            Y[p.perm()] = y.cpu().numpy()
+            err = max(err, float(scaled_error(Y, ref, s).max()))
+        out[name] = {"us": round(wall * 1e6, 2), "GFLOPs": round(2.0 * out["nnz"] * n_rhs / wall / 1e9, 2),
+                     "n_er_pieces": int(sum(p.stats()["n_er_pieces"] for p in plans)),
+                     "max_scaled_error_vs_fp64": err}
+        log(f"power-law batch {name}: {out[name]}")
+        del batch, plans, Xd, Yd
+    return out
 
 
 def run_predictor(args):

@@ -169,8 +169,8 @@ typedef struct {
     int32_t n_er_wide;        /* wide residual slices (one long row, 64 lanes) */
     int32_t ell_width_cap;    /* ELL width cap in effect, 0 = none */
     int32_t n_er_pieces;      /* pieces of at most 8 steps the wide residual
-                                 slices are summed in by ehyb_spmv (0 = no
-                                 wide slices) */
+                                 slices are summed in by ehyb_spmv and
+                                 ehyb_spmm_batched (0 = no wide slices) */
     double t_graph_s, t_partition_s, t_reorder_s, t_encode_s; /* host times */
 } ehyb_plan_stats;
 
@@ -322,9 +322,14 @@ EHYB_API ehyb_status ehyb_unpermute_y(const ehyb_plan *plan, const void *y_perm,
  * of about equal bytes, one per XCD, so that neighbouring partitions, which
  * share halo rows of x, run on one XCD's L2; a workgroup whose run is empty
  * takes items from the other runs.  The last workgroup to finish resets the
- * queues, so the launch can be recorded in a HIP graph and replayed.  X_i and Y_i are
- * row-major [n_i][n_rhs] in plan i's permuted order (flag EHYB_VEC_PERMUTED
- * required), element type as for ehyb_spmv. */
+ * queues, so the launch can be recorded in a HIP graph and replayed.  When
+ * plans of the batch have wide residual slices (hub rows, see n_er_pieces),
+ * one launch before the product sums the pieces of all of them, n_rhs sums
+ * per piece, into the batch's blob, as ehyb_spmv does for one plan; the
+ * partitions then add their rows' pieces in a fixed order, so results are
+ * bitwise deterministic, and with n_rhs == 1 equal to ehyb_spmv's.  X_i and
+ * Y_i are row-major [n_i][n_rhs] in plan i's permuted order (flag
+ * EHYB_VEC_PERMUTED required), element type as for ehyb_spmv. */
 typedef struct ehyb_batch ehyb_batch;
 
 #define EHYB_BATCH_MAX 128   /* matrices per batch */
@@ -334,14 +339,16 @@ typedef struct ehyb_batch ehyb_batch;
  * type, rows_per_wave and n_rhs == `n_rhs` (1, 2, 4 or 8). */
 EHYB_API ehyb_status ehyb_batch_create(const ehyb_plan *const *plans, int32_t n_plans, int32_t n_rhs,
                                       ehyb_batch **out);
-/* Device bytes of the batch descriptor (per-matrix array pointers, work items, queue counters). */
+/* Device bytes of the batch descriptor (per-matrix array pointers, work
+ * items, queue counters, the piece list and the pieces' sums). */
 EHYB_API ehyb_status ehyb_batch_device_bytes(const ehyb_batch *batch, size_t *bytes);
 /* Copy the batch descriptor into `dev_blob` (device, caller-owned, 256-byte
  * aligned); the plans must be uploaded first.  Waits for the copy. */
 EHYB_API ehyb_status ehyb_batch_upload(ehyb_batch *batch, void *dev_blob, size_t bytes, void *stream);
 /* Y_i = A_i X_i for all matrices of the batch, one kernel launch on `stream`.
  * X, Y: host arrays of n_plans device pointers.  Launches on one batch blob
- * must not overlap in time (they share its queue counters). */
+ * must not overlap in time (they share its queue counters and piece sums);
+ * a batch with wide residual slices makes two launches on `stream`. */
 EHYB_API ehyb_status ehyb_spmm_batched(const ehyb_batch *batch, int32_t n_rhs, const void *const *X,
                                       void *const *Y, uint32_t flags, void *stream);
 /* Load mode (ehyb_load_mode) of ehyb_spmm_batched, judged on the batch's

@@ -616,7 +616,7 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
         const V* er_val = static_cast<const V*>(a.er_val);
         const Rsrc r_xg = make_rsrc(x, (uint32_t)((size_t)a.n * sizeof(XR)));
         const i32x4 r_meta = scalar_rsrc(a.er_meta + e0, (uint32_t)ner * 8u);
-        const int nw = (NRHS == 1 && a.er_piece != nullptr) ? a.er_nwide[p] : 0;
+        const int nw = a.er_piece != nullptr ? a.er_nwide[p] : 0;
         const int ngr = (nw + kWave - 1) / kWave;
         const int nitems = ngr + ner - nw;
         // residual slice of item i >= ngr (clamped below for group items, whose metadata is not used)
@@ -626,31 +626,43 @@ __device__ __forceinline__ void process_partition(const PartArrays& a, int p,
         while (it < nitems) {
             const int itn = wave_fetch_add(&Q.q_er, lane);
             const uint2 mn = sload2(r_meta, slice_of(itn) * 8u);
-            if constexpr (NRHS == 1) {
-                if (it < ngr) {
-                    const int k = it * kWave + lane;  // this lane's wide slice
-                    const int e = e0 + min(k, nw - 1);
-                    const int q0 = a.er_piece[e];
-                    const int nq = a.er_piece[e + 1] - q0;  // at least 1
-                    const uint16_t lw = a.er_row[(size_t)e * C];
-                    const Acc* part = static_cast<const Acc*>(a.er_part) + q0;
-                    Acc sum = 0;
-                    // all lanes load kPieceLoads pieces per round (clamped to
-                    // their last piece), so the loads are issued together
-                    for (int j0 = 0; __builtin_amdgcn_ballot_w64(j0 < nq) != 0; j0 += kPieceLoads) {
-                        Acc pv[kPieceLoads];
+            if (it < ngr) {
+                // pieces loaded per round: kPieceLoads, fewer when each is
+                // a row of NRHS sums, to stay within about 32 registers
+                constexpr int kPR = 128 / (NRHS * (int)sizeof(Acc));
+                constexpr int kPL = NRHS == 1 || kPR > kPieceLoads ? kPieceLoads : (kPR > 1 ? kPR : 1);
+                const int k = it * kWave + lane;  // this lane's wide slice
+                const int e = e0 + min(k, nw - 1);
+                const int q0 = a.er_piece[e];
+                const int nq = a.er_piece[e + 1] - q0;  // at least 1
+                const uint16_t lw = a.er_row[(size_t)e * C];
+                const Acc* part = static_cast<const Acc*>(a.er_part) + (size_t)q0 * NRHS;
+                Acc sum[NRHS];
 #pragma unroll
-                        for (int u = 0; u < kPieceLoads; ++u) pv[u] = part[min(j0 + u, nq - 1)];
+                for (int kk = 0; kk < NRHS; ++kk) sum[kk] = 0;
+                // all lanes load kPL pieces per round (clamped to their last
+                // piece), so the loads are issued together
+                for (int j0 = 0; __builtin_amdgcn_ballot_w64(j0 < nq) != 0; j0 += kPL) {
+                    Acc pv[kPL][NRHS];
 #pragma unroll
-                        for (int u = 0; u < kPieceLoads; ++u)
-                            if (j0 + u < nq) sum += pv[u];
-                    }
-                    if (k < nw && lw != 0xFFFF) yer[lw] = sum;
-                    wave_signal_n(&Q.n_er_done, lane, min(kWave, nw - it * kWave));
-                    it = itn;
-                    m = mn;
-                    continue;
+                    for (int u = 0; u < kPL; ++u)
+#pragma unroll
+                        for (int kk = 0; kk < NRHS; ++kk) pv[u][kk] = part[(size_t)min(j0 + u, nq - 1) * NRHS + kk];
+#pragma unroll
+                    for (int u = 0; u < kPL; ++u)
+                        if (j0 + u < nq) {
+#pragma unroll
+                            for (int kk = 0; kk < NRHS; ++kk) sum[kk] += pv[u][kk];
+                        }
                 }
+                if (k < nw && lw != 0xFFFF) {
+#pragma unroll
+                    for (int kk = 0; kk < NRHS; ++kk) yer[(size_t)lw * NRHS + kk] = sum[kk];
+                }
+                wave_signal_n(&Q.n_er_done, lane, min(kWave, nw - it * kWave));
+                it = itn;
+                m = mn;
+                continue;
             }
             const int es = (int)slice_of(it);
             const uint32_t off = __builtin_amdgcn_readfirstlane(m.x);
@@ -792,57 +804,110 @@ __global__ void __launch_bounds__(1024) ehyb_spmm_batched_kernel(BatchArgs args)
     }
 }
 
-// The wide residual slices of ehyb_spmv (one right-hand side), summed before
-// the product over the whole device: one wavefront per piece of at most
-// kPieceSteps steps.  Entry k of a wide slice is at slot off + k, so piece
-// (e, t0, t1) holds slots off + 64*t0 .. off + 64*t1 - 1, one per lane per
-// step; each lane sums its entries in step order, then the wavefront adds
-// its lanes in a fixed tree.  The partition's workgroup adds the pieces of
-// its row in a fixed order, so results do not depend on timing.  All loads
-// are issued unconditionally through views of the piece (steps past its end
-// read column 0 and value 0 without a memory access, and gather x[0]), so
-// that the gathers are in flight together; only the multiply-adds of real
-// steps are guarded.
-template <int DT, bool NT>
-__global__ void __launch_bounds__(256) er_pieces_kernel(const uint2* __restrict__ er_meta,
-                                                        const void* __restrict__ er_val_,
-                                                        const int32_t* __restrict__ er_col,
-                                                        const int32_t* __restrict__ pieces, int n_pieces,
-                                                        const void* __restrict__ x_, uint32_t x_bytes,
-                                                        void* __restrict__ part_) {
+// The wide residual slices, summed before the product over the whole device:
+// one wavefront per piece of at most kPieceSteps steps.  Entry k of a wide
+// slice is at slot off + k, so piece (e, t0, t1) holds slots off + 64*t0 ..
+// off + 64*t1 - 1, one per lane per step; each lane sums its entries in step
+// order, then the wavefront adds its lanes in a fixed tree.  The partition's
+// workgroup adds the pieces of its row in a fixed order, so results do not
+// depend on timing.  All loads are issued unconditionally through views of
+// the piece (steps past its end read column 0 and value 0 without a memory
+// access, and gather x[0]), so that the gathers are in flight together; only
+// the multiply-adds of real steps are guarded.  With NRHS right-hand sides
+// each gather is a row of NRHS elements and lane 0 writes NRHS sums.
+template <int DT, int NRHS, bool NT>
+__device__ __forceinline__ void piece_sum(const uint2* __restrict__ er_meta, const void* __restrict__ er_val_,
+                                          const int32_t* __restrict__ er_col, int e, int t0, int t1,
+                                          const void* __restrict__ x, uint32_t x_bytes, void* __restrict__ out) {
     using P = Prec<DT>;
     using V = typename P::V;
     using X = typename P::X;
     using Acc = typename P::A;
+    using XR = typename Row<X, NRHS>::type;
+    // steps whose gathers are in flight together: the whole piece, or half
+    // of it when each gather is a row of more than 32 bytes
+    constexpr int kPS = sizeof(XR) > 32 ? kPieceSteps / 2 : kPieceSteps;
     const V* er_val = static_cast<const V*>(er_val_);
-    const X* x = static_cast<const X*>(x_);
     const int lane = threadIdx.x & (kWave - 1);
-    const int q = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
-    if (q >= n_pieces) return;
-    const int e = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q]);
-    const int t0 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 1]);
-    const int t1 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 2]);
     const size_t base = (size_t)__builtin_amdgcn_readfirstlane(er_meta[e].x) + (size_t)t0 * kWave;
     const uint32_t nst = (uint32_t)(t1 - t0);
     const Rsrc rc = make_rsrc(er_col + base, nst * (uint32_t)(kWave * sizeof(int32_t)));
     const Rsrc rv = make_rsrc(er_val + base, nst * (uint32_t)(kWave * sizeof(V)));
     const Rsrc rx = make_rsrc(x, x_bytes);
-    int32_t c[kPieceSteps];
-    V v[kPieceSteps];
+    Acc acc[NRHS];
 #pragma unroll
-    for (int j = 0; j < kPieceSteps; ++j) {
-        c[j] = buf_load<int32_t, NT>(rc, lane * (uint32_t)sizeof(int32_t), (uint32_t)j * (uint32_t)(kWave * sizeof(int32_t)));
-        v[j] = buf_load<V, NT>(rv, lane * (uint32_t)sizeof(V), (uint32_t)j * (uint32_t)(kWave * sizeof(V)));
+    for (int k = 0; k < NRHS; ++k) acc[k] = 0;
+#pragma unroll
+    for (int s0 = 0; s0 < kPieceSteps; s0 += kPS) {
+        int32_t c[kPS];
+        V v[kPS];
+#pragma unroll
+        for (int j = 0; j < kPS; ++j) {
+            c[j] = buf_load<int32_t, NT>(rc, lane * (uint32_t)sizeof(int32_t),
+                                         (uint32_t)(s0 + j) * (uint32_t)(kWave * sizeof(int32_t)));
+            v[j] = buf_load<V, NT>(rv, lane * (uint32_t)sizeof(V), (uint32_t)(s0 + j) * (uint32_t)(kWave * sizeof(V)));
+        }
+        XR xg[kPS];
+#pragma unroll
+        for (int j = 0; j < kPS; ++j) xg[j] = buf_load<XR>(rx, (uint32_t)c[j] * (uint32_t)sizeof(XR));
+#pragma unroll
+        for (int j = 0; j < kPS; ++j)
+            if (t0 + s0 + j < t1) {
+                const Acc vv = P::value(v[j]);
+#pragma unroll
+                for (int k = 0; k < NRHS; ++k) acc[k] = fma(vv, (Acc)lane_of<X, NRHS>(xg[j], k), acc[k]);
+            }
     }
-    X xg[kPieceSteps];
 #pragma unroll
-    for (int j = 0; j < kPieceSteps; ++j) xg[j] = buf_load<X>(rx, (uint32_t)c[j] * (uint32_t)sizeof(X));
-    Acc acc = 0;
+    for (int k = 0; k < NRHS; ++k) acc[k] = reduce_lanes<kWave>(acc[k]);
+    if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < kPieceSteps; ++j)
-        if (t0 + j < t1) acc = fma(P::value(v[j]), (Acc)xg[j], acc);
-    acc = reduce_lanes<kWave>(acc);
-    if (lane == 0) static_cast<Acc*>(part_)[q] = acc;
+        for (int k = 0; k < NRHS; ++k) static_cast<Acc*>(out)[k] = acc[k];
+    }
+}
+
+// ehyb_spmv: the pieces of one plan, sums in piece order.
+template <int DT, bool NT>
+__global__ void __launch_bounds__(256) er_pieces_kernel(const uint2* __restrict__ er_meta,
+                                                        const void* __restrict__ er_val,
+                                                        const int32_t* __restrict__ er_col,
+                                                        const int32_t* __restrict__ pieces, int n_pieces,
+                                                        const void* __restrict__ x, uint32_t x_bytes,
+                                                        void* __restrict__ part) {
+    using Acc = typename Prec<DT>::A;
+    const int q = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (q >= n_pieces) return;
+    const int e = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q]);
+    const int t0 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 1]);
+    const int t1 = __builtin_amdgcn_readfirstlane(pieces[3 * (size_t)q + 2]);
+    piece_sum<DT, 1, NT>(er_meta, er_val, er_col, e, t0, t1, x, x_bytes, static_cast<Acc*>(part) + q);
+}
+
+// ehyb_spmm_batched: the pieces of every matrix of the batch in one launch.
+struct BatchPieceArgs {
+    const PartArrays* mats;         // [n_mats]
+    const int4* items;              // (matrix, residual slice, first step, end step), by matrix, then piece
+    int32_t n_items;
+    void* part;                     // [n_items][NRHS] sums, item order
+    const void* X[EHYB_BATCH_MAX];  // row-major [n_i][NRHS], permuted order
+};
+
+template <int DT, int NRHS, bool NT>
+__global__ void __launch_bounds__(256) er_pieces_batched_kernel(BatchPieceArgs args) {
+    using X = typename Prec<DT>::X;
+    using Acc = typename Prec<DT>::A;
+    // read in place: X is indexed at run time (see ehyb_spmm_batched_kernel)
+    const BatchPieceArgs& a = *(const BatchPieceArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+    (void)args;
+    const int q = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)));
+    if (q >= a.n_items) return;
+    const int4 w = a.items[q];
+    const int mi = __builtin_amdgcn_readfirstlane(w.x);
+    const PartArrays& m = a.mats[mi];
+    const uint32_t xb = (uint32_t)((size_t)m.n * NRHS * sizeof(X));  // below 4 GiB: checked by ehyb_spmm_batched
+    piece_sum<DT, NRHS, NT>(m.er_meta, m.er_val, m.er_col, __builtin_amdgcn_readfirstlane(w.y),
+                            __builtin_amdgcn_readfirstlane(w.z), __builtin_amdgcn_readfirstlane(w.w), a.X[mi], xb,
+                            static_cast<Acc*>(a.part) + (size_t)q * NRHS);
 }
 
 template <int DT>
@@ -861,6 +926,26 @@ void launch_pieces(const ehyb_plan& P, bool nt, const void* x, hipStream_t s) {
     else
         hipLaunchKernelGGL((er_pieces_kernel<DT, false>), dim3(nblocks), dim3(256), 0, s, meta, blob + Ly.er_val, col,
                            pc, P.n_pieces, x, xb, part);
+}
+
+template <int DT, int NRHS>
+void launch_pieces_batched_r(bool nt, const BatchPieceArgs& a, hipStream_t s) {
+    const int nblocks = (a.n_items + 3) / 4;  // four wavefronts per 256-thread workgroup
+    if (nt)
+        hipLaunchKernelGGL((er_pieces_batched_kernel<DT, NRHS, true>), dim3(nblocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((er_pieces_batched_kernel<DT, NRHS, false>), dim3(nblocks), dim3(256), 0, s, a);
+}
+
+template <int DT>
+bool launch_pieces_batched(int nrhs, bool nt, const BatchPieceArgs& a, hipStream_t s) {
+    switch (nrhs) {
+        case 1: launch_pieces_batched_r<DT, 1>(nt, a, s); return true;
+        case 2: launch_pieces_batched_r<DT, 2>(nt, a, s); return true;
+        case 4: launch_pieces_batched_r<DT, 4>(nt, a, s); return true;
+        case 8: launch_pieces_batched_r<DT, 8>(nt, a, s); return true;
+        default: return false;
+    }
 }
 
 // Plain CSR SpMV, the comparator (CSR-vector): L lanes per row, rows of a
@@ -1329,15 +1414,29 @@ ehyb_status ehyb_batch_create(const ehyb_plan* const* plans, int32_t n_plans, in
                 int64_t c = 0;
                 for (int32_t sl = P.slice_start[p]; sl < P.slice_start[p + 1]; ++sl)
                     c += (int64_t)(P.ell_meta[4 * (size_t)sl + 1] & 0xFFFFu) * kWave * (P.vbytes + 2);
+                const int32_t ew = P.er_slice_start[p] + (P.n_pieces > 0 ? P.piece_nwide[p] : 0);
                 for (int32_t e = P.er_slice_start[p]; e < P.er_slice_start[p + 1]; ++e)
-                    c += (int64_t)P.er_meta[2 * (size_t)e + 1] * kWave * (P.vbytes + 4);
+                    c += e < ew ? (int64_t)(P.piece_start[e + 1] - P.piece_start[e]) * 8 * n_rhs
+                                : (int64_t)P.er_meta[2 * (size_t)e + 1] * kWave * (P.vbytes + 4);
                 c += 2LL * (P.part_start[p + 1] - P.part_start[p]) * P.xbytes * n_rhs;
                 items.push_back({c, i, p});
                 total_cost += c;
             }
             B->lds_bytes = std::max<int64_t>(B->lds_bytes, lds_bytes_used(P, n_rhs));
-            B->algorithmic_bytes += algorithmic_bytes(P) + 2LL * (n_rhs - 1) * P.n * P.xbytes;
+            B->algorithmic_bytes += algorithmic_bytes(P) + 2LL * (n_rhs - 1) * (P.n * P.xbytes + 8LL * P.n_pieces);
         }
+        // the pieces of every matrix's wide residual slices, summed in one
+        // launch before the product
+        B->pbase.assign((size_t)n_plans + 1, 0);
+        for (int32_t i = 0; i < n_plans; ++i) {
+            const ehyb_plan& P = *B->plans[i];
+            B->pbase[i + 1] = B->pbase[i] + P.n_pieces;
+            for (int32_t q = 0; q < P.n_pieces; ++q) {
+                B->pitems.push_back(i);
+                for (int j = 0; j < 3; ++j) B->pitems.push_back(P.pieces[3 * (size_t)q + j]);
+            }
+        }
+        if (B->pbase[n_plans] > INT32_MAX / 4) return fail(EHYB_EUNSUPPORTED, "more than 2^29 pieces of wide slices");
         if (B->lds_bytes > 160 * 1024 - kStaticLds) return fail(EHYB_EINVAL, "a plan needs more LDS than a workgroup has");
         if (items.size() > (size_t)INT32_MAX) return fail(EHYB_EUNSUPPORTED, "more than 2^31 work items");
         B->items.reserve(items.size() * 2);
@@ -1361,6 +1460,8 @@ ehyb_status ehyb_batch_create(const ehyb_plan* const* plans, int32_t n_plans, in
         B->off_desc = take(sizeof(PartArrays) * (size_t)n_plans);
         B->off_items = take(B->items.size() * 4);
         B->off_counters = take((kXcds + 1) * kCtrStride * sizeof(int32_t));
+        B->off_pitems = take(B->pitems.size() * 4);
+        B->off_part = take((size_t)B->pbase[n_plans] * n_rhs * acc_bytes(B->value_dtype));
         B->total = off;
         *out = B.release();
         return EHYB_OK;
@@ -1380,12 +1481,20 @@ ehyb_status ehyb_batch_upload(ehyb_batch* B, void* dev_blob, size_t bytes, void*
     if (bytes < B->total) return fail(EHYB_EINVAL, "device blob smaller than ehyb_batch_device_bytes");
     if (!is_aligned(dev_blob, kBlobAlign)) return fail(EHYB_EINVAL, "device blob must be 256-byte aligned");
     std::vector<PartArrays> desc;
-    for (const ehyb_plan* P : B->plans) {
+    char* b = (char*)dev_blob;
+    for (size_t i = 0; i < B->plans.size(); ++i) {
+        const ehyb_plan* P = B->plans[i];
         if (!P->dev_blob) return fail(EHYB_ESTATE, "every plan of a batch must be uploaded first");
         desc.push_back(part_arrays(*P));
+        if (P->n_pieces > 0) {
+            // wide slices: piece ranges from the plan, sums in the batch's blob
+            const char* pb = (const char*)P->dev_blob;
+            desc.back().er_piece = (const int32_t*)(pb + P->layout.piece_start);
+            desc.back().er_nwide = (const int32_t*)(pb + P->layout.piece_nwide);
+            desc.back().er_part = b + B->off_part + (size_t)B->pbase[i] * B->n_rhs * acc_bytes(B->value_dtype);
+        }
     }
     hipStream_t s = (hipStream_t)stream;
-    char* b = (char*)dev_blob;
     const std::vector<int32_t> zeros((kXcds + 1) * kCtrStride, 0);
     hipError_t e = hipMemcpyAsync(b + B->off_desc, desc.data(), desc.size() * sizeof(PartArrays),
                                   hipMemcpyHostToDevice, s);
@@ -1393,6 +1502,8 @@ ehyb_status ehyb_batch_upload(ehyb_batch* B, void* dev_blob, size_t bytes, void*
         e = hipMemcpyAsync(b + B->off_items, B->items.data(), B->items.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(b + B->off_counters, zeros.data(), zeros.size() * sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !B->pitems.empty())
+        e = hipMemcpyAsync(b + B->off_pitems, B->pitems.data(), B->pitems.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return fail(EHYB_EDEVICE, std::string("batch upload: ") + hipGetErrorString(e));
     B->dev_blob = dev_blob;
@@ -1440,6 +1551,26 @@ ehyb_status ehyb_spmm_batched(const ehyb_batch* B, int32_t n_rhs, const void* co
     ehyb_status st = EHYB_OK;
     hipStream_t s = (hipStream_t)stream;
     const size_t lds = (size_t)B->lds_bytes;
+    if (!B->pitems.empty()) {
+        // hub rows: their wide residual slices are summed first, over the whole device
+        BatchPieceArgs pa;
+        std::memset(&pa, 0, sizeof(pa));
+        pa.mats = a.mats;
+        pa.items = (const int4*)(b + B->off_pitems);
+        pa.n_items = (int32_t)(B->pitems.size() / 4);
+        pa.part = (void*)(b + B->off_part);
+        for (size_t i = 0; i < B->plans.size(); ++i) pa.X[i] = X[i];
+        bool pok = false;
+        switch (B->value_dtype) {
+            case EHYB_F64: pok = launch_pieces_batched<EHYB_F64>(n_rhs, nt, pa, s); break;
+            case EHYB_F32: pok = launch_pieces_batched<EHYB_F32>(n_rhs, nt, pa, s); break;
+            case EHYB_BF16: pok = launch_pieces_batched<EHYB_BF16>(n_rhs, nt, pa, s); break;
+            case EHYB_F32_ACC64: pok = launch_pieces_batched<EHYB_F32_ACC64>(n_rhs, nt, pa, s); break;
+            case EHYB_BF16_ACC64: pok = launch_pieces_batched<EHYB_BF16_ACC64>(n_rhs, nt, pa, s); break;
+            default: break;
+        }
+        if (!pok) return fail(EHYB_EUNSUPPORTED, "no batched piece kernel for this value type and n_rhs");
+    }
     switch (B->value_dtype) {
         case EHYB_F64: ok = launch_batched_dt<EHYB_F64>(B->L, n_rhs, nt, a, nblocks, threads, lds, s, st); break;
         case EHYB_F32: ok = launch_batched_dt<EHYB_F32>(B->L, n_rhs, nt, a, nblocks, threads, lds, s, st); break;

@@ -187,7 +187,9 @@ struct ehyb_batch {
     int32_t n_rhs = 1, value_dtype = EHYB_F64, L = 1;
     std::vector<int32_t> items;      // (matrix, partition) pairs, by matrix, then partition
     std::vector<int32_t> range;      // [9] items of each XCD's queue
-    size_t off_desc = 0, off_items = 0, off_counters = 0, total = 0;
+    std::vector<int32_t> pitems;     // (matrix, residual slice, first step, end step) of every piece
+    std::vector<int64_t> pbase;      // [n_plans + 1] first piece of each matrix
+    size_t off_desc = 0, off_items = 0, off_counters = 0, off_pitems = 0, off_part = 0, total = 0;
     void* dev_blob = nullptr;
     int64_t lds_bytes = 0;           // dynamic LDS of one workgroup
     int64_t algorithmic_bytes = 0;   // sum over matrices, n_rhs-wide x and y

@@ -40,6 +40,25 @@ POWERLAW = {
     "x_seed": 3,
 }
 
+# a batch of power-law graphs with hub rows: graph i draws, from generator
+# seed 77, n ~ log-uniform [2e4, 2.5e5], degree exponent ~ U[2.1, 2.5] and
+# mean degree ~ U[10, 40], and is generated with seed 900 + i
+POWERLAW_BATCH = {"count": 12, "seed": 77, "n_lo": 2e4, "n_hi": 2.5e5, "graph_seed": 900}
+
+
+def powerlaw_batch():
+    import numpy as np
+
+    import matgen
+    g = matgen.rng(POWERLAW_BATCH["seed"])
+    out = []
+    for i in range(POWERLAW_BATCH["count"]):
+        n = int(np.exp(g.uniform(np.log(POWERLAW_BATCH["n_lo"]), np.log(POWERLAW_BATCH["n_hi"]))))
+        out.append(matgen.powerlaw(n, exponent=float(g.uniform(2.1, 2.5)), mean_deg=float(g.uniform(10, 40)),
+                                   seed=POWERLAW_BATCH["graph_seed"] + i))
+    return out
+
+
 # the batched product (64 uneven FP32 matrices x 8 right-hand sides): plans
 # within half the LDS, so that two workgroups share a CU
 BATCHED_PARAMS = dict(n_rhs=8, lds_bytes=80 * 1024, halo_rows=0, rows_per_wave=64)

@@ -117,6 +117,30 @@ def test_batched_long_hub_rows(dt, n_rhs):
         assert torch.equal(a.view(torch.int32), b.view(torch.int32))
 
 
+@pytest.mark.parametrize("dt", [EHYB_F64, EHYB_F32])
+def test_batched_hub_rows_match_the_single_product(dt):
+    """With one right-hand side, the batched product of plans whose hub rows
+    are summed in pieces gives the single product's bits: the same pieces,
+    summed in the same order, by the same partition code."""
+    mats = [matgen.powerlaw(60000, exponent=2.2, mean_deg=30, seed=5), matgen.stencil3d(12, perm_seed=1, val_seed=2),
+            matgen.powerlaw(6000, exponent=2.3, mean_deg=8, seed=6)]
+    plans = [Plan(A, value_dtype=dt, halo_rows=-1, rows_per_wave=16, slice_rows=2000).upload("cuda:0") for A in mats]
+    assert plans[0].stats()["n_er_pieces"] > 100 and plans[2].stats()["n_er_pieces"] > 0
+    g = matgen.rng(31)
+    tdt = torch.float64 if dt == EHYB_F64 else torch.float32
+    Xd = [torch.from_numpy(g.uniform(-1, 1, (A.n_rows, 1))).to("cuda:0", tdt) for A in mats]
+    Yd = [torch.empty_like(x) for x in Xd]
+    Batch(plans, 1).spmm(Xd, Yd)
+    for A, p, x, y in zip(mats, plans, Xd, Yd):
+        ys = p.spmv(x[:, 0])
+        torch.cuda.synchronize()
+        assert torch.equal(y[:, 0].view(torch.int32 if dt == EHYB_F32 else torch.int64),
+                           ys.view(torch.int32 if dt == EHYB_F32 else torch.int64)), f"n={A.n_rows}"
+        Xh = np.empty((A.n_rows, 1))
+        Xh[p.perm()] = x.cpu().numpy()
+        _check(A, Xh, _unperm(p, y.cpu().numpy().astype(np.float64)), dt, "hub rows, one right-hand side")
+
+
 def test_repeated_launches_identical():
     mats, plans, X, Xd, Yd, B = _run(EHYB_F32, 8)
     first = [y.clone() for y in Yd]
