@@ -91,16 +91,20 @@ def test_batched_load_modes_identical():
         assert torch.equal(u.view(torch.int32), v.view(torch.int32))
 
 
-@pytest.mark.parametrize("dt,n_rhs", [(EHYB_F32, 8), (EHYB_F64, 2), (EHYB_F64, 8)])
+@pytest.mark.parametrize("dt,n_rhs", [(EHYB_F32, 8), (EHYB_F64, 2), (EHYB_F64, 8), (EHYB_F64, 4), (EHYB_F64, 1),
+                                      (EHYB_BF16, 4), (EHYB_F32, 2)])
 def test_batched_long_hub_rows(dt, n_rhs):
     """Hub rows with wide residual slices of hundreds of steps, in the
-    batched product (n_rhs-wide rows), next to a small matrix."""
+    batched product (n_rhs-wide rows), next to a small matrix: the pieces
+    pre-pass with n_rhs sums per piece, results within the bound and the
+    same bits on a second launch."""
     mats = [matgen.powerlaw(60000, exponent=2.2, mean_deg=30, seed=5), matgen.stencil3d(12, perm_seed=1, val_seed=2)]
     xb = 8 if dt == EHYB_F64 else 4
     plans = [Plan(A, value_dtype=dt, n_rhs=n_rhs, halo_rows=-1, rows_per_wave=16,
                   slice_rows=min(2000, (160 * 1024 - 64) // (2 * xb * n_rhs))).upload("cuda:0") for A in mats]
     m = np.asarray(plans[0].arrays()["er_meta"]).reshape(-1, 2).astype(np.int64)
     assert (((m[:, 1] >> 31) == 1) & ((m[:, 1] & 0x7FFFFFFF) > 32)).any()
+    assert plans[0].stats()["n_er_pieces"] > 0  # summed in pieces before the product
     g = matgen.rng(21)
     X = [g.uniform(-1, 1, (A.n_rows, n_rhs)) for A in mats]
     tdt = torch.float64 if dt == EHYB_F64 else torch.float32
