@@ -732,7 +732,9 @@ def run_batched(args):
         "roofline": {"bound": "hbm", "achieved": round(algo / kern_g / 1e9, 1), "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": round(algo / kern_g / 1e9 / PEAK_HBM_GBPS, 4),
                      "traffic": load_traffic(kernel_source_hash(), "ehyb_spmm_batched_f32x8_64mat_traffic.json"),
-                     "kernel": "ehyb_spmm_batched_kernel<EHYB_F32, L=1, NRHS=8, streaming loads>",
+                     "kernel": "ehyb_spmm_batched_kernel<EHYB_F32, L=1, NRHS=8, streaming loads>"
+                               + (" + er_pieces_batched_kernel (one product)" if any(p.stats()["n_er_pieces"]
+                                                                                   for p in plans) else ""),
                      "algorithmic_bytes": algo, "launch_us": round(kern_g * 1e6, 2)},
         "cpu_baseline": cpu,
         "batched_eager_us": round(wall_e * 1e6, 2),
