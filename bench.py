@@ -837,16 +837,16 @@ def time_powerlaw_batch(args, torch, dev):
 
     import matgen
     from paper_2204_06666_amd import EHYB_F32, EHYB_F64, Batch, Plan
-    from paper_2204_06666_amd.workloads import POWERLAW_BATCH, powerlaw_batch
+    from paper_2204_06666_amd.workloads import POWERLAW_BATCH, POWERLAW_BATCH_F32X8, powerlaw_batch
 
     log("generating the power-law batch")
     mats = powerlaw_batch()
     out = {"workload": f"{POWERLAW_BATCH['count']} Chung-Lu graphs, n log-uniform in [2e4, 2.5e5], exponent "
                        "U[2.1, 2.5], mean degree U[10, 40]",
            "n": int(sum(A.n_rows for A in mats)), "nnz": int(sum(A.nnz for A in mats))}
-    for name, dt, n_rhs, prm in (("f32x8", EHYB_F32, 8, dict(lds_bytes=80 * 1024, halo_rows=0)),
-                                 ("f64x1", EHYB_F64, 1, {})):
-        plans = [Plan(A, value_dtype=dt, n_rhs=n_rhs, rows_per_wave=64, **prm).upload(dev) for A in mats]
+    for name, dt, prm in (("f32x8", EHYB_F32, POWERLAW_BATCH_F32X8), ("f64x1", EHYB_F64, dict(n_rhs=1, rows_per_wave=64))):
+        n_rhs = prm["n_rhs"]
+        plans = [Plan(A, value_dtype=dt, **prm).upload(dev) for A in mats]
         batch = Batch(plans, n_rhs, dev)
         g = matgen.rng(11)
         X = [g.uniform(-1, 1, (A.n_rows, n_rhs)) for A in mats]
@@ -862,9 +862,14 @@ def time_powerlaw_batch(args, torch, dev):
             Y = np.empty((A.n_rows, n_rhs))
             Y[p.perm()] = y.cpu().numpy()
             err = max(err, float(scaled_error(Y, ref, s).max()))
+        xb = 8 if dt == EHYB_F64 else 4
+        algo = sum(p.stats()["algorithmic_bytes"] + 2 * (n_rhs - 1) * p.n * xb for p in plans)
         out[name] = {"us": round(wall * 1e6, 2), "GFLOPs": round(2.0 * out["nnz"] * n_rhs / wall / 1e9, 2),
+                     "algorithmic_bytes": algo, "frac_of_8TBps": round(algo / wall / 8e12, 4),
                      "n_er_pieces": int(sum(p.stats()["n_er_pieces"] for p in plans)),
                      "max_scaled_error_vs_fp64": err}
+        if name == "f32x8":
+            out[name]["traffic"] = load_traffic(kernel_source_hash(), "ehyb_spmm_batched_f32x8_powerlaw12_traffic.json")
         log(f"power-law batch {name}: {out[name]}")
         del batch, plans, Xd, Yd
     return out

@@ -4,6 +4,8 @@ Runs the headline EHYB FP64 product (or, with ``--workload batched``, the
 batched product of 64 FP32 matrices x 8 right-hand sides; with ``--workload
 powerlaw``, the FP64 product of the 2.5e5-row power-law graph with hub rows,
 default plan: the hub-row pre-pass, then the product; with ``--workload
+powerlaw-batched``, the batched FP32 product of 12 power-law graphs x 8
+right-hand sides, pre-pass and product; with ``--workload
 knnfem``, the products of the 3e6-row kNN-FEM matrix with FP64, FP32 and
 BF16 values, one after the other) `--reps` times and
 the copy probe on a buffer of known size `--reps` times, nothing else on the GPU, so that the
@@ -30,7 +32,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--reps", type=int, default=5)
     ap.add_argument("--copy-mib", type=int, default=256)
-    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "batched", "powerlaw", "knnfem"])
+    ap.add_argument("--workload", default="stencil27", choices=["stencil27", "batched", "powerlaw", "powerlaw-batched", "knnfem"])
     ap.add_argument("--cache-dir", default=None, help="knnfem: keep the matrix and plans here between runs")
     args = ap.parse_args()
     import torch
@@ -58,6 +60,18 @@ def main():
         xp = torch.from_numpy(x[plan.perm()]).to(dev)
         yp = torch.empty_like(xp)
         run = lambda: plan.spmv(xp, yp)  # noqa: E731
+    elif args.workload == "powerlaw-batched":
+        from paper_2204_06666_amd import EHYB_F32, Batch
+        from paper_2204_06666_amd.workloads import POWERLAW_BATCH_F32X8, powerlaw_batch
+        mats = powerlaw_batch()
+        nrhs = POWERLAW_BATCH_F32X8["n_rhs"]
+        plans = [Plan(A, value_dtype=EHYB_F32, **POWERLAW_BATCH_F32X8).upload(dev) for A in mats]
+        batch = Batch(plans, nrhs, dev)
+        g = matgen.rng(11)
+        Xd = [torch.from_numpy(g.uniform(-1, 1, (A.n_rows, nrhs))).to(dev, torch.float32).contiguous() for A in mats]
+        Yd = [torch.empty_like(v) for v in Xd]
+        algo = sum(p.stats()["algorithmic_bytes"] + 2 * (nrhs - 1) * p.n * 4 for p in plans)
+        run = lambda: batch.spmm(Xd, Yd)  # noqa: E731
     elif args.workload == "knnfem":
         import numpy as np
 

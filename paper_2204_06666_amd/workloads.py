@@ -44,6 +44,8 @@ POWERLAW = {
 # seed 77, n ~ log-uniform [2e4, 2.5e5], degree exponent ~ U[2.1, 2.5] and
 # mean degree ~ U[10, 40], and is generated with seed 900 + i
 POWERLAW_BATCH = {"count": 12, "seed": 77, "n_lo": 2e4, "n_hi": 2.5e5, "graph_seed": 900}
+# its FP32 plans for 8 right-hand sides (two workgroups per CU, no halo)
+POWERLAW_BATCH_F32X8 = dict(n_rhs=8, lds_bytes=80 * 1024, halo_rows=0, rows_per_wave=64)
 
 
 def powerlaw_batch():

@@ -38,6 +38,7 @@ def test_traffic_evidence_is_for_the_current_kernel_source():
     source as it stands; bench.py reports them only then."""
     h = bench.kernel_source_hash()
     for name in ("ehyb_spmv_f64_stencil27_traffic.json", "ehyb_spmm_batched_f32x8_64mat_traffic.json",
+                 "ehyb_spmm_batched_f32x8_powerlaw12_traffic.json",
                  "ehyb_spmv_f64_powerlaw250k_traffic.json", "ehyb_spmv_f64_knnfem_traffic.json",
                  "ehyb_spmv_f32_knnfem_traffic.json", "ehyb_spmv_bf16_knnfem_traffic.json"):
         t = bench.load_traffic(h, name)

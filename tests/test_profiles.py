@@ -12,7 +12,8 @@ PROFILES = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__
 
 
 @pytest.mark.parametrize("name,limit", [("ehyb_spmv_f64_stencil27_traffic.json", 1.10),
-                                        ("ehyb_spmm_batched_f32x8_64mat_traffic.json", 1.30),
+                                        ("ehyb_spmm_batched_f32x8_64mat_traffic.json", 1.10),
+                                        ("ehyb_spmm_batched_f32x8_powerlaw12_traffic.json", 2.30),
                                         ("ehyb_spmv_f64_powerlaw250k_traffic.json", 1.35),
                                         ("ehyb_spmv_f64_knnfem_traffic.json", 1.05),
                                         ("ehyb_spmv_f32_knnfem_traffic.json", 1.05),
@@ -35,6 +36,7 @@ def test_measured_traffic_close_to_algorithmic(name, limit):
 
 
 @pytest.mark.parametrize("name", ["ehyb_spmv_f64_stencil27_traffic.json", "ehyb_spmm_batched_f32x8_64mat_traffic.json",
+                                  "ehyb_spmm_batched_f32x8_powerlaw12_traffic.json",
                                   "ehyb_spmv_f64_powerlaw250k_traffic.json", "ehyb_spmv_f64_knnfem_traffic.json",
                                   "ehyb_spmv_f32_knnfem_traffic.json", "ehyb_spmv_bf16_knnfem_traffic.json"])
 def test_lds_counters_recorded(name):
