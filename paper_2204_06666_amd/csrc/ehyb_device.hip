@@ -867,9 +867,11 @@ __device__ __forceinline__ void piece_sum(const uint2* __restrict__ er_meta, con
     }
 }
 
-// ehyb_spmv: the pieces of one plan, sums in piece order.
+// ehyb_spmv: the pieces of one plan, sums in piece order.  One wavefront
+// per workgroup: on a power-law graph the product was 1.4% faster than
+// with four per workgroup, and 4% slower with sixteen.
 template <int DT, bool NT>
-__global__ void __launch_bounds__(256) er_pieces_kernel(const uint2* __restrict__ er_meta,
+__global__ void __launch_bounds__(64) er_pieces_kernel(const uint2* __restrict__ er_meta,
                                                         const void* __restrict__ er_val,
                                                         const int32_t* __restrict__ er_col,
                                                         const int32_t* __restrict__ pieces, int n_pieces,
@@ -915,17 +917,17 @@ template <int DT>
 void launch_pieces(const ehyb_plan& P, bool nt, const void* x, hipStream_t s) {
     const char* blob = (const char*)P.dev_blob;
     const BlobLayout& Ly = P.layout;
-    const int nblocks = (P.n_pieces + 3) / 4;  // four wavefronts per 256-thread workgroup
+    const int nblocks = P.n_pieces;  // one wavefront per workgroup
     const uint2* meta = (const uint2*)(blob + Ly.er_meta);
     const int32_t* col = (const int32_t*)(blob + Ly.er_col);
     const int32_t* pc = (const int32_t*)(blob + Ly.pieces);
     void* part = (void*)(blob + Ly.ypart);
     const uint32_t xb = (uint32_t)((size_t)P.n * P.xbytes);  // below 4 GiB: checked by ehyb_spmv
     if (nt)
-        hipLaunchKernelGGL((er_pieces_kernel<DT, true>), dim3(nblocks), dim3(256), 0, s, meta, blob + Ly.er_val, col, pc,
+        hipLaunchKernelGGL((er_pieces_kernel<DT, true>), dim3(nblocks), dim3(64), 0, s, meta, blob + Ly.er_val, col, pc,
                            P.n_pieces, x, xb, part);
     else
-        hipLaunchKernelGGL((er_pieces_kernel<DT, false>), dim3(nblocks), dim3(256), 0, s, meta, blob + Ly.er_val, col,
+        hipLaunchKernelGGL((er_pieces_kernel<DT, false>), dim3(nblocks), dim3(64), 0, s, meta, blob + Ly.er_val, col,
                            pc, P.n_pieces, x, xb, part);
 }
 
